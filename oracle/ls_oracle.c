@@ -1,0 +1,417 @@
+/*
+ * ls_oracle.c -- plain, slow CPU reference ("the oracle") for iterative sketching, the randomized
+ * least-squares solver of E. N. Epperly, "Fast and forward stable randomized algorithms for linear
+ * least-squares problems" (arXiv 2311.04362).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this library.  It shares no code, header or constant table with the GPU library;
+ * the two meet only in the seeded input arrays they are both given.
+ *
+ * Everything is IEEE double, straight loops in the order the definitions state them, compiled
+ * with -ffp-contract=off so that no multiply-add is fused behind the reader's back.  Matrices are
+ * row-major with an explicit leading dimension (elements between two rows).
+ *
+ * Functions and the passages they follow:
+ *   orc_splitmix64          SplitMix64 output (Steele, Lea & Flood, OOPSLA 2014) -- the random
+ *                           source of the sparse-sign embedding (the paper leaves it open)
+ *   orc_sparse_sign         sparse-sign embedding S, eq. (sparse_sign), Section 2.2
+ *   orc_sketch              B = S A and S b, Algorithm 2 (second line)
+ *   orc_householder_lstsq   Householder-QR least squares, Section 2.1 (backward-stable reference,
+ *                           eq. ls_backward); also the sketch-and-solve start, eq. (sketched_ls)
+ *   orc_residual_gradient   r_i = b - A x_i and c_i = A^T r_i, Algorithm 2 loop body
+ *   orc_solve_rt/orc_solve_r the two triangular solves of Algorithm 2, Section 3.2
+ *   orc_iterative_sketching Algorithm 2 end to end
+ *   orc_iterative_sketching_dm  Algorithm 2 with damping / momentum, eq. (damping_momentum)
+ *   orc_normest / orc_condest_1 / orc_dimension   Section 3.3 implementation guidance
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea & Flood 2014).  The generator's state advances by the odd constant
+ * 0x9E3779B97F4A7C15 per output and each output is the state passed through the finalizer below
+ * (the published "mix64" with shifts 30/27/31).  Output k (k = 0, 1, ...) of the stream seeded
+ * with `seed` is therefore mix64(seed + (k+1) * gamma): the stream is counter-based. */
+static uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
+{
+    return orc_mix64(seed + (k + 1ULL) * 0x9E3779B97F4A7C15ULL);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sparse-sign embedding, eq. (sparse_sign): S = zeta^{-1/2} [s_1 ... s_m], each column s_j of
+ * length d holding exactly zeta nonzeros equal to +-1 at uniformly random (distinct) positions.
+ *
+ * Bit-level reading of "uniformly random positions" and "uniform +-1":
+ *   column j consumes outputs k = j*2^16 + t, t = 0, 1, 2, ... of the SplitMix64 stream `seed`;
+ *   a draw z proposes row (z >> 11) mod d; a row already taken by this column is rejected and the
+ *   next draw is used; an accepted draw fixes that entry's sign: -1 if bit 0 of z is set, else +1.
+ *   Should all 2^16 draws of a column be spent (only conceivable when d is close to zeta), the
+ *   column is completed with the smallest free rows, sign +1.
+ * Output: rows[j*zeta + e], signs[j*zeta + e] for the e-th accepted entry of column j. */
+#define ORC_DRAWS_PER_COLUMN 65536ULL
+
+int orc_sparse_sign(int64_t m, int64_t d, int32_t zeta, uint64_t seed, int32_t *rows, int8_t *signs)
+{
+    if (m < 0 || d < 1 || zeta < 1 || zeta > d) return 1;
+    for (int64_t j = 0; j < m; ++j) {
+        int32_t *rj = rows + j * zeta;
+        int8_t *sj = signs + j * zeta;
+        int32_t got = 0;
+        for (uint64_t t = 0; got < zeta && t < ORC_DRAWS_PER_COLUMN; ++t) {
+            uint64_t z = orc_splitmix64(seed, (uint64_t)j * ORC_DRAWS_PER_COLUMN + t);
+            int32_t row = (int32_t)((z >> 11) % (uint64_t)d);
+            int dup = 0;
+            for (int32_t e = 0; e < got; ++e) dup |= (rj[e] == row);
+            if (dup) continue;
+            rj[got] = row;
+            sj[got] = (z & 1ULL) ? -1 : 1;
+            ++got;
+        }
+        for (int32_t row = 0; got < zeta; ++row) {
+            int dup = 0;
+            for (int32_t e = 0; e < got; ++e) dup |= (rj[e] == row);
+            if (!dup) { rj[got] = row; sj[got] = 1; ++got; }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sketch, Algorithm 2 ("B <- S A"), together with S b (the same S embeds range([A b]),
+ * Section 2.3).  By the definition of the product, B[k,:] = sum_j S[k,j] A[j,:].  The loop runs
+ * over j in ascending order, so each row of B receives its terms in ascending j.  The entries of S
+ * are +-zeta^{-1/2}; the common factor fl(1/sqrt(zeta)) is applied once to each finished sum
+ * (adding +-A[j,:] is exact, so the only roundings are the additions and that one product). */
+int orc_sketch(int64_t m, int64_t n, const double *A, int64_t lda, const double *b, int64_t d,
+               int32_t zeta, uint64_t seed, double *B, int64_t ldb, double *Sb)
+{
+    if (n < 1 || lda < n || ldb < n || d < 1 || zeta < 1 || zeta > d) return 1;
+    int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1) * (size_t)zeta);
+    int8_t *signs = (int8_t *)malloc(sizeof(int8_t) * (size_t)(m > 0 ? m : 1) * (size_t)zeta);
+    if (!rows || !signs) { free(rows); free(signs); return 2; }
+    orc_sparse_sign(m, d, zeta, seed, rows, signs);
+    for (int64_t k = 0; k < d; ++k) {
+        for (int64_t c = 0; c < n; ++c) B[k * ldb + c] = 0.0;
+        if (Sb) Sb[k] = 0.0;
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        for (int32_t e = 0; e < zeta; ++e) {
+            int64_t k = rows[j * zeta + e];
+            double s = (double)signs[j * zeta + e];
+            for (int64_t c = 0; c < n; ++c) B[k * ldb + c] += s * A[j * lda + c];
+            if (Sb && b) Sb[k] += s * b[j];
+        }
+    }
+    double scale = 1.0 / sqrt((double)zeta);
+    for (int64_t k = 0; k < d; ++k) {
+        for (int64_t c = 0; c < n; ++c) B[k * ldb + c] *= scale;
+        if (Sb) Sb[k] *= scale;
+    }
+    free(rows);
+    free(signs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Back substitution R x = y for upper-triangular R (n x n). */
+void orc_solve_r(int64_t n, const double *R, int64_t ldr, const double *y, double *x)
+{
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int64_t k = i + 1; k < n; ++k) s -= R[i * ldr + k] * x[k];
+        x[i] = s / R[i * ldr + i];
+    }
+}
+
+/* Forward substitution R^T y = c (R^T is lower triangular; its row i is column i of R). */
+void orc_solve_rt(int64_t n, const double *R, int64_t ldr, const double *c, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = c[i];
+        for (int64_t k = 0; k < i; ++k) s -= R[k * ldr + i] * y[k];
+        y[i] = s / R[i * ldr + i];
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Householder-QR least squares (the textbook method of Section 2.1, backward stable):
+ * factor W = [M | rhs] (rows x (n+1)) by Householder reflections H_0 ... H_{n-1},
+ *   for k = 0..n-1:  alpha = W[k,k];  sigma = ||W[k:rows, k]||;  beta = -sign(alpha) sigma
+ *                    (sign(0) = +1);  v = W[k:rows, k] - beta e_1;
+ *                    apply H = I - 2 v v^T / (v^T v) to columns k+1..n (rhs included);
+ *                    R[k,k] = beta, R[k,k+1:n] = the updated row k,
+ * then (Q^T rhs)[0:n] = W[0:n, n] and x solves R x = (Q^T rhs)[0:n] by back substitution.
+ * The norm of (Q^T rhs)[n:rows] is ||rhs - M x||.  Q is never formed.
+ * Returns 0, 1 on bad arguments, 2 on allocation failure, 3 + k if column k is exactly zero
+ * after the previous reflections (rank deficient).  R, qtb, x and resid may be NULL. */
+int orc_householder_lstsq(int64_t rows, int64_t n, const double *M, int64_t ldm, const double *rhs,
+                          double *R, int64_t ldr, double *qtb, double *x, double *resid)
+{
+    if (n < 1 || rows < n || ldm < n || (R && ldr < n)) return 1;
+    int64_t w = n + 1;
+    double *W = (double *)malloc(sizeof(double) * (size_t)rows * (size_t)w);
+    double *v = (double *)malloc(sizeof(double) * (size_t)rows);
+    double *wt = (double *)malloc(sizeof(double) * (size_t)w);
+    double *Rl = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    if (!W || !v || !wt || !Rl) { free(W); free(v); free(wt); free(Rl); return 2; }
+    for (int64_t i = 0; i < rows; ++i) {
+        for (int64_t c = 0; c < n; ++c) W[i * w + c] = M[i * ldm + c];
+        W[i * w + n] = rhs ? rhs[i] : 0.0;
+    }
+    memset(Rl, 0, sizeof(double) * (size_t)n * (size_t)n);
+    int rc = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        double alpha = W[k * w + k];
+        double ss = 0.0;
+        for (int64_t i = k; i < rows; ++i) ss += W[i * w + k] * W[i * w + k];
+        double sigma = sqrt(ss);
+        if (sigma == 0.0) { rc = 3 + (int)k; break; }
+        double beta = (alpha >= 0.0) ? -sigma : sigma;
+        v[k] = alpha - beta;
+        for (int64_t i = k + 1; i < rows; ++i) v[i] = W[i * w + k];
+        double vtv = 0.0;
+        for (int64_t i = k; i < rows; ++i) vtv += v[i] * v[i];
+        /* w_l = v^T W[k:rows, l] for l = k+1..n, accumulated in row order */
+        for (int64_t l = k + 1; l < w; ++l) wt[l] = 0.0;
+        for (int64_t i = k; i < rows; ++i)
+            for (int64_t l = k + 1; l < w; ++l) wt[l] += v[i] * W[i * w + l];
+        for (int64_t l = k + 1; l < w; ++l) wt[l] = 2.0 * wt[l] / vtv;
+        for (int64_t i = k; i < rows; ++i)
+            for (int64_t l = k + 1; l < w; ++l) W[i * w + l] -= wt[l] * v[i];
+        Rl[k * n + k] = beta;
+        for (int64_t l = k + 1; l < n; ++l) Rl[k * n + l] = W[k * w + l];
+        W[k * w + k] = beta;
+        for (int64_t i = k + 1; i < rows; ++i) W[i * w + k] = 0.0;
+    }
+    if (rc == 0) {
+        for (int64_t l = 0; l < n; ++l) wt[l] = W[l * w + n];
+        if (qtb) for (int64_t l = 0; l < n; ++l) qtb[l] = wt[l];
+        if (resid) {
+            double s = 0.0;
+            for (int64_t i = n; i < rows; ++i) s += W[i * w + n] * W[i * w + n];
+            *resid = sqrt(s);
+        }
+        if (x) orc_solve_r(n, Rl, n, wt, x);
+        if (R)
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t c = 0; c < n; ++c) R[i * ldr + c] = Rl[i * n + c];
+    }
+    free(W); free(v); free(wt); free(Rl);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One evaluation of the right-hand side of the refinement step, Algorithm 2 loop body, in the
+ * stable form of Section 3.2: first the residual r = b - A x (each (A x)_i summed over columns in
+ * order, then subtracted from b_i), then c = A^T r (each c_l summed over rows in order).  The
+ * algebraically equal A^T b - A^T (A x) is the unstable "bad residual" variant and is not used.
+ * rnorm2 (nullable) receives sum_i r_i^2. */
+void orc_residual_gradient(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                           const double *x, double *c, double *rnorm2)
+{
+    double rr = 0.0;
+    for (int64_t l = 0; l < n; ++l) c[l] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double ax = 0.0;
+        for (int64_t l = 0; l < n; ++l) ax += A[i * lda + l] * x[l];
+        double r = b[i] - ax;
+        rr += r * r;
+        for (int64_t l = 0; l < n; ++l) c[l] += A[i * lda + l] * r;
+    }
+    if (rnorm2) *rnorm2 = rr;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Iterative sketching, Algorithm 2:
+ *   S <- d x m sparse-sign embedding;  B <- S A;  (Q, R) <- QR(B, 'econ');
+ *   x_0 <- R^{-1} (Q^T (S b))                      (sketch-and-solve start, eq. sketched_ls)
+ *   for i = 0..q-1:  r_i <- b - A x_i;  c_i <- A^T r_i;  d_i <- R^{-1} (R^{-T} c_i);
+ *                    x_{i+1} <- x_i + d_i.
+ * Outputs x (= x_q); optional x_hist ((q+1) x n: x_0..x_q), R (n x n, ldr), rnorm2_hist (q
+ * entries: ||r_i||^2).  Return codes as orc_householder_lstsq. */
+int orc_iterative_sketching(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                            int64_t d, int32_t zeta, uint64_t seed, int32_t q, double *x,
+                            double *x_hist, double *R_out, int64_t ldr, double *rnorm2_hist)
+{
+    if (n < 1 || m < n || d < n || q < 0 || lda < n) return 1;
+    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)n);
+    double *Sb = (double *)malloc(sizeof(double) * (size_t)d);
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dv = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 2;
+    if (!B || !Sb || !R || !c || !y || !dv) goto done;
+    rc = orc_sketch(m, n, A, lda, b, d, zeta, seed, B, n, Sb);
+    if (rc) goto done;
+    rc = orc_householder_lstsq(d, n, B, n, Sb, R, n, NULL, x, NULL);
+    if (rc) goto done;
+    if (x_hist) memcpy(x_hist, x, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < q; ++i) {
+        orc_residual_gradient(m, n, A, lda, b, x, c, rnorm2_hist ? &rnorm2_hist[i] : NULL);
+        orc_solve_rt(n, R, n, c, y);
+        orc_solve_r(n, R, n, y, dv);
+        for (int64_t l = 0; l < n; ++l) x[l] = x[l] + dv[l];
+        if (x_hist) memcpy(x_hist + (size_t)(i + 1) * (size_t)n, x, sizeof(double) * (size_t)n);
+    }
+    if (R_out)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t l = 0; l < n; ++l) R_out[i * ldr + l] = R[i * n + l];
+done:
+    free(B); free(Sb); free(R); free(c); free(y); free(dv);
+    return rc;
+}
+
+/* Iterative sketching with damping or momentum, eq. (damping_momentum): the same loop with the
+ * update x_{i+1} = x_i + alpha d_i + beta (x_i - x_{i-1}); the first step takes x_{-1} = x_0.
+ * Damping (eq. damping): alpha = (1-eps^2)^2/(1+eps^2), beta = 0; momentum (eq. momentum):
+ * alpha = (1-eps^2)^2, beta = eps^2 (the caller passes alpha and beta). */
+int orc_iterative_sketching_dm(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                               int64_t d, int32_t zeta, uint64_t seed, int32_t q, double alpha,
+                               double beta, double *x, double *x_hist)
+{
+    if (n < 1 || m < n || d < n || q < 0 || lda < n) return 1;
+    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)n);
+    double *Sb = (double *)malloc(sizeof(double) * (size_t)d);
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dv = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xprev = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 2;
+    if (!B || !Sb || !R || !c || !y || !dv || !xprev) goto done;
+    rc = orc_sketch(m, n, A, lda, b, d, zeta, seed, B, n, Sb);
+    if (rc) goto done;
+    rc = orc_householder_lstsq(d, n, B, n, Sb, R, n, NULL, x, NULL);
+    if (rc) goto done;
+    memcpy(xprev, x, sizeof(double) * (size_t)n);
+    if (x_hist) memcpy(x_hist, x, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < q; ++i) {
+        orc_residual_gradient(m, n, A, lda, b, x, c, NULL);
+        orc_solve_rt(n, R, n, c, y);
+        orc_solve_r(n, R, n, y, dv);
+        for (int64_t l = 0; l < n; ++l) {
+            double xn = x[l] + alpha * dv[l] + beta * (x[l] - xprev[l]);
+            xprev[l] = x[l];
+            x[l] = xn;
+        }
+        if (x_hist) memcpy(x_hist + (size_t)(i + 1) * (size_t)n, x, sizeof(double) * (size_t)n);
+    }
+done:
+    free(B); free(Sb); free(R); free(c); free(y); free(dv); free(xprev);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Section 3.3 guidance, used by the stopping rule.
+ * normest: ||R|| estimated by `steps` steps of the power method on R^T R from the start vector g
+ * (the caller passes a Gaussian g): v <- g/||g||; repeat: w = R v, v' = R^T w, est = ||w||,
+ * v = v'/||v'||.  Returns the last ||R v||. */
+double orc_normest(int64_t n, const double *R, int64_t ldr, const double *g, int32_t steps)
+{
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double est = 0.0, s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += g[i] * g[i];
+    s = sqrt(s);
+    for (int64_t i = 0; i < n; ++i) v[i] = g[i] / s;
+    for (int32_t it = 0; it < steps; ++it) {
+        double ww = 0.0;
+        for (int64_t i = 0; i < n; ++i) {          /* w = R v (R upper) */
+            double a = 0.0;
+            for (int64_t k = i; k < n; ++k) a += R[i * ldr + k] * v[k];
+            w[i] = a;
+            ww += a * a;
+        }
+        est = sqrt(ww);
+        double vv = 0.0;
+        for (int64_t k = 0; k < n; ++k) {          /* v = R^T w */
+            double a = 0.0;
+            for (int64_t i = 0; i <= k; ++i) a += R[i * ldr + k] * w[i];
+            v[k] = a;
+            vv += a * a;
+        }
+        vv = sqrt(vv);
+        if (vv == 0.0) break;
+        for (int64_t k = 0; k < n; ++k) v[k] /= vv;
+    }
+    free(v); free(w);
+    return est;
+}
+
+/* ||T^{-1}||_1 estimate for T in {R, R^T} by Hager's method (Higham, Accuracy and Stability,
+ * Ch. 15, Alg. 15.3 without the extra vector): start x = e/n; repeat: y = T^{-1} x;
+ * xi = sign(y); z = T^{-T} xi; if ||z||_inf <= z^T x stop; else x = e_j, j = argmax |z_j|.
+ * Used as condest(R) = ||R||_1 * est(||R^{-1}||_1). */
+static double orc_inv_norm1_est(int64_t n, const double *R, int64_t ldr)
+{
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
+    double est = 0.0;
+    for (int it = 0; it < 5; ++it) {
+        orc_solve_r(n, R, ldr, x, y);               /* y = R^{-1} x */
+        est = 0.0;
+        for (int64_t i = 0; i < n; ++i) est += fabs(y[i]);
+        for (int64_t i = 0; i < n; ++i) y[i] = (y[i] >= 0.0) ? 1.0 : -1.0;
+        orc_solve_rt(n, R, ldr, y, z);              /* z = R^{-T} xi */
+        int64_t jmax = 0;
+        double zmax = 0.0, ztx = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (fabs(z[i]) > zmax) { zmax = fabs(z[i]); jmax = i; }
+            ztx += z[i] * x[i];
+        }
+        if (zmax <= ztx) break;
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        x[jmax] = 1.0;
+    }
+    free(x); free(y); free(z);
+    return est;
+}
+
+double orc_condest_1(int64_t n, const double *R, int64_t ldr)
+{
+    double n1 = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int64_t i = 0; i <= k; ++i) s += fabs(R[i * ldr + k]);
+        if (s > n1) n1 = s;
+    }
+    return n1 * orc_inv_norm1_est(n, R, ldr);
+}
+
+/* Principal branch W_0 of the Lambert W function for x >= 0 by Newton's method on w e^w = x. */
+static double orc_lambert_w0(double x)
+{
+    double w = (x < 1.0) ? x : log(x) - log(log(x) + 1.0);
+    if (w < 0.0) w = 0.0;
+    for (int it = 0; it < 100; ++it) {
+        double ew = exp(w);
+        double f = w * ew - x;
+        double wn = w - f / (ew * (w + 1.0));
+        if (fabs(wn - w) <= 1e-15 * (1.0 + fabs(wn))) { w = wn; break; }
+        w = wn;
+    }
+    return w;
+}
+
+/* Embedding dimension of eq. (dimension):
+ *   d = max(ceil((6+4 sqrt 2) n exp(W((6-4 sqrt 2) (m/n^2) log(1/u)))), 20 n). */
+int64_t orc_dimension(int64_t m, int64_t n, double u)
+{
+    double a = 6.0 + 4.0 * sqrt(2.0), c = 6.0 - 4.0 * sqrt(2.0);
+    double arg = c * ((double)m / ((double)n * (double)n)) * log(1.0 / u);
+    double dd = ceil(a * (double)n * exp(orc_lambert_w0(arg)));
+    int64_t d = (int64_t)dd;
+    return d > 20 * n ? d : 20 * n;
+}
