@@ -1,0 +1,154 @@
+/*
+ * ls.h -- C ABI of libls, an MI355X (gfx950) implementation of iterative sketching, the randomized
+ * least-squares solver of E. N. Epperly, "Fast and forward stable randomized algorithms for linear
+ * least-squares problems" (arXiv 2311.04362).
+ *
+ * Problem (eq. ls):  x = argmin_y ||b - A y||  for full-rank A (m x n), m >= n.
+ * Method (Algorithm 2):  S <- d x m sparse-sign embedding;  B <- S A;  (Q, R) <- QR(B);
+ *   x_0 <- R^{-1} Q^T (S b);  for i < q:  r_i = b - A x_i;  c_i = A^T r_i;
+ *   d_i = R^{-1} (R^{-T} c_i);  x_{i+1} = x_i + d_i.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are row-major: element (i, j) of a matrix with leading dimension ld is at [i*ld + j].
+ *  - All array arguments are DEVICE pointers on the context's GPU, allocated and freed by the
+ *    caller; they must be 8-byte aligned.  The library owns only its internal workspace.
+ *  - `stream` is a hipStream_t (NULL: the device's null stream).  Every call enqueues its work on
+ *    that stream and returns without waiting, except ls_sync and ls_solve (which waits to report).
+ *  - Argument errors are reported synchronously (LS_ERR_ARG) before anything is enqueued.
+ *    Conditions the GPU detects (rank deficiency, NaN/Inf) are deferred: they are collected in a
+ *    device status word and returned by the next ls_sync on that context.
+ *  - Nothing aborts and no exception crosses the ABI.  ls_last_error gives a readable detail.
+ *  - Results are deterministic: the same inputs, options and seed give bitwise-identical outputs
+ *    (no floating-point atomics; every reduction has a fixed order).
+ *  - A context is not thread-safe; use one per host thread.  Calls on one context that overlap
+ *    on different streams share its workspace and must be ordered by the caller.
+ */
+#ifndef LS_H
+#define LS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LS_OK = 0,
+    LS_ERR_ARG = 1,          /* invalid argument (synchronous)                                   */
+    LS_ERR_ALLOC = 2,        /* device allocation failed                                         */
+    LS_ERR_DEVICE = 3,       /* HIP runtime error, or no usable device                           */
+    LS_ERR_RANK = 4,         /* deferred: |R_kk| <= n u max_j |R_jj| (A taken as rank deficient) */
+    LS_ERR_NONFINITE = 5,    /* deferred: NaN or Inf met in B, R or x                            */
+    LS_ERR_DIVERGED = 6,     /* deferred: the stopping rule saw the residual grow without bound  */
+    LS_ERR_UNSUPPORTED = 7   /* a size outside what this build handles (see ls_limits)           */
+} ls_status;
+
+typedef struct ls_ctx ls_ctx;
+
+/* Limits of this build (returned by ls_limits). */
+#define LS_MAX_ZETA 32       /* nonzeros per column of S                                         */
+#define LS_MAX_N 2048        /* columns of A                                                     */
+
+/* Context: binds a GPU, its compiled kernels, a growable workspace and the status word.
+ * device >= 0 selects a GPU.  device = -1 creates a host-only context that validates arguments
+ * and then returns LS_ERR_DEVICE from every compute call (for testing argument checks without a
+ * GPU).  Returns LS_ERR_DEVICE if the GPU cannot be used. */
+ls_status ls_create(int device, ls_ctx **out);
+void ls_destroy(ls_ctx *ctx);                       /* frees the workspace; NULL is a no-op   */
+const char *ls_last_error(const ls_ctx *ctx);       /* detail of the last failure, never NULL  */
+ls_status ls_limits(int32_t *max_zeta, int32_t *max_n);
+
+/* Options (ls_set_option / ls_get_option).  Integer options take ival, real ones dval. */
+enum {
+    LS_OPT_ZETA = 1,        /* nonzeros per column of S used by ls_solve (default 8, Sec. 3.3)   */
+    LS_OPT_SEED = 2,        /* seed of S used by ls_solve (default 0)                           */
+    LS_OPT_UPDATE = 3,      /* 0: x += d (Alg. 2); 1: damping; 2: momentum (eq. damping_momentum) */
+    LS_OPT_ALPHA = 4,       /* alpha of the damping/momentum update (dval; <= 0: from eps)      */
+    LS_OPT_BETA = 5,        /* beta of the momentum update (dval; < 0: from eps)                */
+    LS_OPT_PRECISION = 6,   /* 0: FP64 throughout; 1: sketch, QR and R-solves in FP32           */
+    LS_OPT_PROFILE = 7      /* 1: time every launch of the fused pass kernel with HIP events    */
+};
+ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval);
+ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval);
+
+/* ---- Sparse-sign embedding (eq. sparse_sign, Section 2.2) -------------------------------------
+ * S = zeta^{-1/2} [s_1 ... s_m] (d x m); column s_j holds zeta distinct nonzeros +-1.  Positions and
+ * signs come from the counter-based SplitMix64 stream `seed` (Steele, Lea & Flood 2014): column j
+ * uses outputs j*2^16 + t, t = 0, 1, ...; a draw z proposes row (z >> 11) mod d, a repeated row is
+ * rejected, an accepted draw gives sign -1 if bit 0 of z is set, else +1; a column that exhausted
+ * its 2^16 draws is completed with the smallest free rows, sign +1.
+ *
+ * ls_sketch_embedding writes the nonzeros column by column, in acceptance order:
+ *   rows[j*zeta + e] (int32, in [0, d)), signs[j*zeta + e] (int8, +-1), j < m, e < zeta.
+ * Requires m >= 1, 1 <= zeta <= min(d, LS_MAX_ZETA), d < 2^31, m*zeta < 2^31. */
+ls_status ls_sketch_embedding(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t zeta,
+                              uint64_t seed, int32_t *rows, int8_t *signs);
+
+/* The same S transposed into compressed rows: for sketch row k, entries rowptr[k] .. rowptr[k+1]-1
+ * of `cols` hold the columns j with S[k, j] != 0 in ascending j; bit 31 of an entry is set when
+ * S[k, j] < 0 and bits 0..30 hold j.  rowptr has d+1 entries, cols has m*zeta. */
+ls_status ls_sketch_csr(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t zeta,
+                        uint64_t seed, int32_t *rowptr, int32_t *cols);
+
+/* ---- Sketch (Algorithm 2, "B <- S A"; S b for the sketch-and-solve start, eq. sketched_ls) ------
+ * B (d x n, ldb >= n) = S A and Sb (d) = S b for A (m x n, lda >= n), b (m).  Row k of B is the sum
+ * of +-A[j, :] over the columns j of sketch row k in ascending j, then multiplied once by
+ * fl(1/sqrt(zeta)).  Gathered by rows of A; no atomics.  b and Sb may both be NULL.
+ * Requires n >= 1, m >= 1, d >= 1, lda >= n, ldb >= n and the embedding limits above. */
+ls_status ls_sketch(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                    const double *b, int64_t d, int32_t zeta, uint64_t seed, double *B, int64_t ldb,
+                    double *Sb);
+
+/* ---- Householder QR of the sketch and the sketch-and-solve start (Alg. 2, third and fourth
+ * lines; eq. it-sk-qr, eq. sketched_ls) --------------------------------------------------------
+ * Factors [B | Sb] (d x (n+1)) by blocked Householder reflections (compact-WY trailing updates on
+ * FP64 matrix cores).  Q is never formed: Q^T is applied to Sb as the last column.
+ * Writes R (n x n upper triangular, ldr >= n; the strict lower triangle is set to zero) and
+ * x0 = R^{-1} (Q^T Sb)[0:n] (n, nullable).  R[k,k] = -sign(alpha) * ||column||, sign(0) = +1.
+ * B and Sb are read only (the factorization works on a copy in the workspace).
+ * Deferred: LS_ERR_RANK if |R_kk| <= n u max|R_jj|; LS_ERR_NONFINITE on NaN/Inf in R or x0.
+ * Requires 1 <= n <= LS_MAX_N, d >= n, ldb >= n. */
+ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const double *B,
+                       int64_t ldb, const double *Sb, double *R, int64_t ldr, double *x0);
+
+/* ---- One evaluation of the refinement right-hand side (Alg. 2 loop, stable form of Sec. 3.2) ----
+ * c = A^T (b - A x) with the residual formed first, in FP64, and never stored; rnorm2 (nullable,
+ * one double) = ||b - A x||^2.  A is read once.  Requires 1 <= n <= LS_MAX_N, m >= 1, lda >= n. */
+ls_status ls_gradient(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                      const double *b, const double *x, double *c, double *rnorm2);
+
+/* ---- The two triangular solves of Alg. 2: d = R^{-1} (R^{-T} c) by forward then back
+ * substitution (never an explicit inverse).  R: n x n upper triangular, ldr >= n. */
+ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R, int64_t ldr,
+                           const double *c, double *d);
+
+/* ---- q refinement steps (Alg. 2 loop; eq. it-sk-it-ref) ---------------------------------------
+ * x (n, in: x_i, out: x_{i+q}) is updated q times by x <- x + R^{-1} R^{-T} A^T (b - A x).
+ * rnorm2 (nullable, q doubles) receives ||b - A x_i||^2 for each step.  q = 0 leaves x unchanged.
+ * With LS_OPT_UPDATE = 1 or 2 the update is x_{i+1} = x_i + alpha d_i + beta (x_i - x_{i-1})
+ * (eq. damping_momentum) with x_{-1} = x_i on entry; eps = sqrt(n/d) needs d, so these options
+ * take explicit LS_OPT_ALPHA / LS_OPT_BETA here.  Requires q >= 0 and the ls_gradient limits. */
+ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                     const double *b, const double *R, int64_t ldr, double *x, int32_t q,
+                     double *rnorm2);
+
+/* ---- Whole solve (Algorithm 2) ------------------------------------------------------------------
+ * x (n) = x_q for A (m x n, lda), b (m), embedding dimension d (d <= 0: d = 20 n) and q steps,
+ * with zeta and seed from the options.  Enqueues sketch, QR and iterations, then waits on `stream`
+ * and returns the deferred status (as ls_sync).  Requires d >= n and the limits above. */
+ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                   const double *b, int64_t d, int32_t q, double *x);
+
+/* Waits for `stream`, then returns and clears the deferred device status of the context. */
+ls_status ls_sync(ls_ctx *ctx, void *stream);
+
+/* Kernel timing (LS_OPT_PROFILE = 1): every launch of the fused pass kernel (the A^T (b - A x)
+ * pass of ls_gradient, ls_iterate and ls_solve) is bracketed by HIP events on the caller's stream.
+ * ls_profile waits for the recorded events and returns the summed kernel time in milliseconds and
+ * the number of launches since the last reset (reset != 0 clears the counters afterwards). */
+ls_status ls_profile(ls_ctx *ctx, double *pass_ms, int64_t *pass_launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_H */

@@ -65,6 +65,8 @@ def lib():
         L.orc_normest.argtypes = [_i64, _D, _i64, _D, _i32]
         L.orc_condest_1.restype = ctypes.c_double
         L.orc_condest_1.argtypes = [_i64, _D, _i64]
+        L.orc_sketch_row.restype = None
+        L.orc_sketch_row.argtypes = [_i64, _i64, _D, _i64, _I8, _i32, _D]
         L.orc_dimension.restype = ctypes.c_int64
         L.orc_dimension.argtypes = [_i64, _i64, ctypes.c_double]
         _lib = L
@@ -111,6 +113,16 @@ def sketch(A, b, n: int, d: int, zeta: int, seed: int):
     if rc:
         raise ValueError(f"orc_sketch failed (rc={rc})")
     return B, Sb
+
+
+def sketch_row(rows, signs, zeta: int):
+    """zeta^{-1/2} * sum_t signs[t] rows[t, :], summed in the given order."""
+    rows = _f64(rows)
+    signs = np.ascontiguousarray(signs, dtype=np.int8)
+    cnt, n = rows.shape
+    out = np.zeros(n)
+    lib().orc_sketch_row(cnt, n, _dp(rows), n, signs.ctypes.data_as(_I8), zeta, _dp(out))
+    return out
 
 
 def householder_lstsq(M, rhs, n: int | None = None):

@@ -415,3 +415,19 @@ int64_t orc_dimension(int64_t m, int64_t n, double u)
     int64_t d = (int64_t)dd;
     return d > 20 * n ? d : 20 * n;
 }
+
+/* One row of the sketch from its terms: out = fl(1/sqrt(zeta)) * sum_t sign_t * rows[t, :], summed
+ * in the order given (the caller passes the terms of sketch row k in ascending column j of S, as
+ * the full product orc_sketch accumulates them).  Lets a test check sampled rows of a sketch whose
+ * A is too large to sketch on the CPU. */
+void orc_sketch_row(int64_t cnt, int64_t n, const double *rows, int64_t ldr, const int8_t *signs,
+                    int32_t zeta, double *out)
+{
+    for (int64_t c = 0; c < n; ++c) out[c] = 0.0;
+    for (int64_t t = 0; t < cnt; ++t) {
+        double s = (double)signs[t];
+        for (int64_t c = 0; c < n; ++c) out[c] += s * rows[t * ldr + c];
+    }
+    double scale = 1.0 / sqrt((double)zeta);
+    for (int64_t c = 0; c < n; ++c) out[c] *= scale;
+}

@@ -1,0 +1,533 @@
+// Host side of libls: the C ABI declared in include/ls.h.  Validates arguments synchronously,
+// sizes the context workspace, and enqueues the kernels of sketch.hip, qr.hip and iterate.hip on
+// the caller's stream.  Device-detected conditions accumulate in a status word read by ls_sync.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace {
+
+const char *kNullCtx = "null context";
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Makes the context's device current for the duration of a call and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+ls_status check_embedding(ls_ctx *ctx, int64_t m, int64_t d, int32_t zeta)
+{
+    if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
+    if (d < 1 || d >= (int64_t(1) << 31)) return ls_fail(ctx, LS_ERR_ARG, "d must be in [1, 2^31)");
+    if (zeta < 1 || zeta > LS_MAX_ZETA || zeta > d)
+        return ls_fail(ctx, LS_ERR_ARG, "zeta must be in [1, min(d, LS_MAX_ZETA)]");
+    if (m * (int64_t)zeta >= (int64_t(1) << 31))
+        return ls_fail(ctx, LS_ERR_UNSUPPORTED, "m*zeta must be < 2^31");
+    return LS_OK;
+}
+
+ls_status check_mat(ls_ctx *ctx, const void *p, int64_t ld, int64_t n, const char *name)
+{
+    if (!p) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is NULL");
+    if (!aligned(p, 8)) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+    if (ld < n) return ls_fail(ctx, LS_ERR_ARG, std::string("leading dimension of ") + name + " < n");
+    return LS_OK;
+}
+
+ls_status check_vec(ls_ctx *ctx, const void *p, const char *name, bool nullable = false)
+{
+    if (!p) return nullable ? LS_OK : ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is NULL");
+    if (!aligned(p, 8)) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+    return LS_OK;
+}
+
+ls_status check_n(ls_ctx *ctx, int64_t n)
+{
+    if (n < 1) return ls_fail(ctx, LS_ERR_ARG, "n must be >= 1");
+    if (n > LS_MAX_N) return ls_fail(ctx, LS_ERR_UNSUPPORTED, "n exceeds LS_MAX_N");
+    return LS_OK;
+}
+
+#define LS_TRY(expr)                   \
+    do {                               \
+        ls_status st_ = (expr);        \
+        if (st_ != LS_OK) return st_;  \
+    } while (0)
+
+#define HIP_TRY(ctx, expr, what)                              \
+    do {                                                      \
+        ls_status st_ = ls_hip_check((ctx), (expr), (what));  \
+        if (st_ != LS_OK) return st_;                         \
+    } while (0)
+
+ls_status need_device(ls_ctx *ctx)
+{
+    if (ctx->device < 0) return ls_fail(ctx, LS_ERR_DEVICE, "host-only context: no device work");
+    return LS_OK;
+}
+
+// Two-pass arena: size with base == nullptr, grow the workspace, then carve for real.
+template <class F>
+ls_status with_arena(ls_ctx *ctx, F &&carve)
+{
+    Arena sizing;
+    carve(sizing);
+    LS_TRY(ls_ensure_ws(ctx, sizing.off + 256));
+    Arena real;
+    real.base = static_cast<char *>(ctx->ws);
+    carve(real);
+    return LS_OK;
+}
+
+ls_status do_embedding(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
+                       const SketchBufs &sb, bool csr)
+{
+    HIP_TRY(ctx, launch_sparse_sign(s, m, d, zeta, seed, sb), "sparse-sign kernel");
+    if (csr) HIP_TRY(ctx, launch_csr(s, m, d, zeta, sb), "CSR kernels");
+    return LS_OK;
+}
+
+// Next start/end event pair for a timed pass launch (nullptr pair when profiling is off).
+ls_status pass_events(ls_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1)
+{
+    e0 = e1 = nullptr;
+    if (!ctx->profile) return LS_OK;
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(ctx, hipEventCreate(&e), "create event");
+        ctx->ev_pool.push_back(e);
+    }
+    e0 = ctx->ev_pool[ctx->ev_used];
+    e1 = ctx->ev_pool[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    return LS_OK;
+}
+
+ls_status timed_gradient(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A,
+                         int64_t lda, const double *b, const double *x, const IterBufs &ib,
+                         double *c, double *rnorm2)
+{
+    hipEvent_t e0, e1;
+    LS_TRY(pass_events(ctx, e0, e1));
+    HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, c, rnorm2, e0, e1), "pass kernels");
+    return LS_OK;
+}
+
+void update_params(const ls_ctx *ctx, int64_t n, int64_t d, int &mode, double &alpha, double &beta)
+{
+    mode = 1;
+    alpha = 1.0;
+    beta = 0.0;
+    if (ctx->update == 0) return;
+    const double eps2 = (d > 0) ? (double)n / (double)d : 0.0;   // eps = sqrt(n/d)
+    mode = 2;
+    if (ctx->update == 1) {            // damping, eq. (damping)
+        alpha = (ctx->alpha > 0.0) ? ctx->alpha : (1.0 - eps2) * (1.0 - eps2) / (1.0 + eps2);
+        beta = 0.0;
+    } else {                           // momentum, eq. (momentum)
+        alpha = (ctx->alpha > 0.0) ? ctx->alpha : (1.0 - eps2) * (1.0 - eps2);
+        beta = (ctx->beta >= 0.0) ? ctx->beta : eps2;
+    }
+}
+
+}  // namespace
+
+ls_status ls_fail(ls_ctx *ctx, ls_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+ls_status ls_hip_check(ls_ctx *ctx, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return LS_OK;
+    return ls_fail(ctx, LS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->ws_bytes) return LS_OK;
+    // The old block may still be read by queued work: drain the device before releasing it.
+    HIP_TRY(ctx, hipDeviceSynchronize(), "synchronize before workspace growth");
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    const size_t want = bytes + bytes / 4;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return ls_fail(ctx, LS_ERR_ALLOC, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        ctx->ws_bytes = bytes;
+    } else {
+        ctx->ws_bytes = want;
+    }
+    ctx->ws = p;
+    return LS_OK;
+}
+
+extern "C" {
+
+ls_status ls_limits(int32_t *max_zeta, int32_t *max_n)
+{
+    if (max_zeta) *max_zeta = LS_MAX_ZETA;
+    if (max_n) *max_n = LS_MAX_N;
+    return LS_OK;
+}
+
+ls_status ls_create(int device, ls_ctx **out)
+{
+    if (!out) return LS_ERR_ARG;
+    *out = nullptr;
+    ls_ctx *ctx = new (std::nothrow) ls_ctx;
+    if (!ctx) return LS_ERR_ALLOC;
+    if (device == -1) {
+        *out = ctx;
+        return LS_OK;
+    }
+    int count = 0;
+    if (device < 0 || hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        (void)hipGetLastError();
+        delete ctx;
+        return LS_ERR_DEVICE;
+    }
+    ctx->device = device;
+    DeviceGuard g(device);
+    if (!g.ok || hipMalloc(&ctx->status, sizeof(int32_t)) != hipSuccess ||
+        hipMemset(ctx->status, 0, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(&ctx->status_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->status) (void)hipFree(ctx->status);
+        delete ctx;
+        return LS_ERR_DEVICE;
+    }
+    *out = ctx;
+    return LS_OK;
+}
+
+void ls_destroy(ls_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->device >= 0) {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->status) (void)hipFree(ctx->status);
+        if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+        for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+}
+
+const char *ls_last_error(const ls_ctx *ctx)
+{
+    if (!ctx) return kNullCtx;
+    return ctx->err.c_str();
+}
+
+ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval)
+{
+    if (!ctx) return LS_ERR_ARG;
+    switch (key) {
+    case LS_OPT_ZETA:
+        if (ival < 1 || ival > LS_MAX_ZETA) return ls_fail(ctx, LS_ERR_ARG, "zeta out of range");
+        ctx->zeta = (int32_t)ival;
+        return LS_OK;
+    case LS_OPT_SEED: ctx->seed = (uint64_t)ival; return LS_OK;
+    case LS_OPT_UPDATE:
+        if (ival < 0 || ival > 2) return ls_fail(ctx, LS_ERR_ARG, "update must be 0, 1 or 2");
+        ctx->update = (int32_t)ival;
+        return LS_OK;
+    case LS_OPT_ALPHA:
+        if (!std::isfinite(dval)) return ls_fail(ctx, LS_ERR_ARG, "alpha must be finite");
+        ctx->alpha = dval;
+        return LS_OK;
+    case LS_OPT_BETA:
+        if (!std::isfinite(dval)) return ls_fail(ctx, LS_ERR_ARG, "beta must be finite");
+        ctx->beta = dval;
+        return LS_OK;
+    case LS_OPT_PRECISION:
+        if (ival != 0) return ls_fail(ctx, LS_ERR_UNSUPPORTED, "only FP64 (precision 0) is built");
+        ctx->precision = 0;
+        return LS_OK;
+    case LS_OPT_PROFILE:
+        if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "profile must be 0 or 1");
+        ctx->profile = (int32_t)ival;
+        return LS_OK;
+    default: return ls_fail(ctx, LS_ERR_ARG, "unknown option key");
+    }
+}
+
+ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval)
+{
+    if (!ctx) return LS_ERR_ARG;
+    int64_t iv = 0;
+    double dv = 0.0;
+    switch (key) {
+    case LS_OPT_ZETA: iv = ctx->zeta; break;
+    case LS_OPT_SEED: iv = (int64_t)ctx->seed; break;
+    case LS_OPT_UPDATE: iv = ctx->update; break;
+    case LS_OPT_ALPHA: dv = ctx->alpha; break;
+    case LS_OPT_BETA: dv = ctx->beta; break;
+    case LS_OPT_PRECISION: iv = ctx->precision; break;
+    case LS_OPT_PROFILE: iv = ctx->profile; break;
+    default: return LS_ERR_ARG;
+    }
+    if (ival) *ival = iv;
+    if (dval) *dval = dv;
+    return LS_OK;
+}
+
+ls_status ls_sketch_embedding(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t zeta,
+                              uint64_t seed, int32_t *rows, int8_t *signs)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_embedding(ctx, m, d, zeta));
+    if (!rows || !signs || !aligned(rows, 4)) return ls_fail(ctx, LS_ERR_ARG, "rows/signs NULL or misaligned");
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SketchBufs sb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, false));
+    HIP_TRY(ctx, launch_unpack_embedding(s, m, zeta, sb.ent, rows, signs), "unpack kernel");
+    return LS_OK;
+}
+
+ls_status ls_sketch_csr(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
+                        int32_t *rowptr, int32_t *cols)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_embedding(ctx, m, d, zeta));
+    if (!rowptr || !cols || !aligned(rowptr, 4) || !aligned(cols, 4))
+        return ls_fail(ctx, LS_ERR_ARG, "rowptr/cols NULL or misaligned");
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SketchBufs sb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, true));
+    HIP_TRY(ctx, hipMemcpyAsync(rowptr, sb.rowptr, sizeof(int32_t) * (size_t)(d + 1), hipMemcpyDeviceToDevice, s), "copy rowptr");
+    HIP_TRY(ctx, hipMemcpyAsync(cols, sb.cols, sizeof(int32_t) * (size_t)(m * zeta), hipMemcpyDeviceToDevice, s), "copy cols");
+    return LS_OK;
+}
+
+ls_status ls_sketch(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                    const double *b, int64_t d, int32_t zeta, uint64_t seed, double *B, int64_t ldb,
+                    double *Sb)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    LS_TRY(check_embedding(ctx, m, d, zeta));
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_mat(ctx, B, ldb, n, "B"));
+    if ((b == nullptr) != (Sb == nullptr)) return ls_fail(ctx, LS_ERR_ARG, "b and Sb must both be given or both NULL");
+    LS_TRY(check_vec(ctx, b, "b", true));
+    LS_TRY(check_vec(ctx, Sb, "Sb", true));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SketchBufs sb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, true));
+    const double scale = 1.0 / std::sqrt((double)zeta);
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1), "gather kernel");
+    return LS_OK;
+}
+
+ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const double *B, int64_t ldb,
+                       const double *Sb, double *R, int64_t ldr, double *x0)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
+    LS_TRY(check_mat(ctx, B, ldb, n, "B"));
+    LS_TRY(check_vec(ctx, Sb, "Sb"));
+    LS_TRY(check_mat(ctx, R, ldr, n, "R"));
+    LS_TRY(check_vec(ctx, x0, "x0", true));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    QrBufs qb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb); }));
+    HIP_TRY(ctx, launch_copy_sketch(s, d, n, B, ldb, Sb, qb), "copy sketch");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status), "QR kernels");
+    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, ldr, ctx->status), "extract R");
+    if (x0) HIP_TRY(ctx, launch_back_substitution(s, n, R, ldr, qb.RT, qb.qtb, x0, ctx->status), "x0 solve");
+    return LS_OK;
+}
+
+ls_status ls_gradient(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                      const double *b, const double *x, double *c, double *rnorm2)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_vec(ctx, b, "b"));
+    LS_TRY(check_vec(ctx, x, "x"));
+    LS_TRY(check_vec(ctx, c, "c"));
+    LS_TRY(check_vec(ctx, rnorm2, "rnorm2", true));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    IterBufs ib{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { iter_bufs(ar, m, n, ib, false); }));
+    LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, c, rnorm2));
+    return LS_OK;
+}
+
+ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R, int64_t ldr,
+                           const double *c, double *d)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    LS_TRY(check_mat(ctx, R, ldr, n, "R"));
+    LS_TRY(check_vec(ctx, c, "c"));
+    LS_TRY(check_vec(ctx, d, "d"));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *RT = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { RT = ar.take<double>((size_t)n * (size_t)n); }));
+    HIP_TRY(ctx, launch_transpose(s, n, R, ldr, RT), "transpose R");
+    HIP_TRY(ctx, launch_solve_update(s, n, R, ldr, RT, c, nullptr, nullptr, d, 0, 0.0, 0.0, ctx->status), "solve kernel");
+    return LS_OK;
+}
+
+ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                     const double *b, const double *R, int64_t ldr, double *x, int32_t q,
+                     double *rnorm2)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
+    if (q < 0) return ls_fail(ctx, LS_ERR_ARG, "q must be >= 0");
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_vec(ctx, b, "b"));
+    LS_TRY(check_mat(ctx, R, ldr, n, "R"));
+    LS_TRY(check_vec(ctx, x, "x"));
+    LS_TRY(check_vec(ctx, rnorm2, "rnorm2", true));
+    if (ctx->update != 0 && !(ctx->alpha > 0.0))
+        return ls_fail(ctx, LS_ERR_ARG, "damping/momentum in ls_iterate needs LS_OPT_ALPHA (and LS_OPT_BETA)");
+    LS_TRY(need_device(ctx));
+    if (q == 0) return LS_OK;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    IterBufs ib{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { iter_bufs(ar, m, n, ib, true); }));
+    int mode;
+    double alpha, beta;
+    update_params(ctx, n, 0, mode, alpha, beta);
+    if (ctx->update == 2 && ctx->beta < 0.0) return ls_fail(ctx, LS_ERR_ARG, "momentum in ls_iterate needs LS_OPT_BETA");
+    HIP_TRY(ctx, launch_transpose(s, n, R, ldr, ib.RT), "transpose R");
+    if (mode == 2)
+        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
+    for (int32_t i = 0; i < q; ++i) {
+        LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, rnorm2 ? rnorm2 + i : nullptr));
+        HIP_TRY(ctx, launch_solve_update(s, n, R, ldr, ib.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status), "solve kernel");
+    }
+    return LS_OK;
+}
+
+ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                   const double *b, int64_t d, int32_t q, double *x)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (m < n) return ls_fail(ctx, LS_ERR_ARG, "m must be >= n");
+    if (d <= 0) d = 20 * n;
+    if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
+    if (q < 0) return ls_fail(ctx, LS_ERR_ARG, "q must be >= 0");
+    const int32_t zeta = ctx->zeta;
+    LS_TRY(check_embedding(ctx, m, d, zeta));
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_vec(ctx, b, "b"));
+    LS_TRY(check_vec(ctx, x, "x"));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SketchBufs sb{};
+    QrBufs qb{};
+    IterBufs ib{};
+    double *R = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        sketch_bufs(ar, m, d, zeta, sb);
+        qr_bufs(ar, d, n, qb);
+        iter_bufs(ar, m, n, ib, false);
+        R = ar.take<double>((size_t)n * (size_t)n);
+    }));
+    // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
+    const double scale = 1.0 / std::sqrt((double)zeta);
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
+    // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status), "QR kernels");
+    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
+    HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
+    // (c) q refinement steps.
+    int mode;
+    double alpha, beta;
+    update_params(ctx, n, d, mode, alpha, beta);
+    if (mode == 2 && q > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
+    for (int32_t i = 0; i < q; ++i) {
+        LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status), "solve kernel");
+    }
+    return ls_sync(ctx, stream);
+}
+
+ls_status ls_sync(ls_ctx *ctx, void *stream)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+    const int32_t st = *ctx->status_host;
+    if (st != 0) {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
+        HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+        if (st & ST_RANK) return ls_fail(ctx, LS_ERR_RANK, "R is numerically singular (rank-deficient A or sketch)");
+        if (st & ST_NONFINITE) return ls_fail(ctx, LS_ERR_NONFINITE, "NaN or Inf in B, R or x");
+        if (st & ST_DIVERGED) return ls_fail(ctx, LS_ERR_DIVERGED, "the residual grew without bound");
+    }
+    return LS_OK;
+}
+
+ls_status ls_profile(ls_ctx *ctx, double *pass_ms, int64_t *pass_launches, int32_t reset)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    double total = 0.0;
+    for (size_t k = 0; k + 1 < ctx->ev_used; k += 2) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev_pool[k + 1]), "event synchronize");
+        float ms = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev_pool[k], ctx->ev_pool[k + 1]), "event elapsed");
+        total += ms;
+    }
+    if (pass_ms) *pass_ms = total;
+    if (pass_launches) *pass_launches = (int64_t)(ctx->ev_used / 2);
+    if (reset) ctx->ev_used = 0;
+    return LS_OK;
+}
+
+}  // extern "C"

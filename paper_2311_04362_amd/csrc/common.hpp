@@ -1,0 +1,112 @@
+// Internal declarations of libls shared by its translation units (host side + kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ls.h"
+
+// Deferred device status bits, OR-ed into the context's status word by kernels.
+enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4 };
+
+struct ls_ctx {
+    int device = -1;                // -1: host-only context (argument checks only)
+    // options
+    int32_t zeta = 8;
+    uint64_t seed = 0;
+    int32_t update = 0;             // 0 plain, 1 damping, 2 momentum
+    double alpha = 0.0;             // <= 0: derived from eps = sqrt(n/d)
+    double beta = -1.0;             // < 0: derived from eps
+    int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves)
+    int32_t profile = 0;            // 1: bracket each fused-pass launch with events
+    std::vector<hipEvent_t> ev_pool; // start/end pairs, reused
+    size_t ev_used = 0;             // events recorded since the last reset (even count)
+    // device memory owned by the library
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t *status = nullptr;      // device status word
+    int32_t *status_host = nullptr; // pinned host copy
+    std::string err;
+};
+
+// Bump allocator over the context workspace: first a sizing pass (base == nullptr), then the real
+// pass over the allocated block.
+struct Arena {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count, size_t align = 256) {
+        off = (off + align - 1) / align * align;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+ls_status ls_fail(ls_ctx *ctx, ls_status st, const std::string &msg);
+ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes);
+ls_status ls_hip_check(ls_ctx *ctx, hipError_t e, const char *what);
+
+// ---- sketch (sketch.hip) -------------------------------------------------------------------------
+struct SketchBufs {
+    uint32_t *ent;       // m*zeta packed (row | sign<<31), column-major by j
+    int32_t *rowcount;   // d
+    int32_t *rowptr;     // d+1
+    int32_t *fill;       // d
+    uint32_t *cols;      // m*zeta packed (j | sign<<31), by sketch row, ascending j
+};
+void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb);
+hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
+                              const SketchBufs &sb);
+hipError_t launch_unpack_embedding(hipStream_t s, int64_t m, int32_t zeta, const uint32_t *ent,
+                                   int32_t *rows, int8_t *signs);
+hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const SketchBufs &sb);
+hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                         const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
+                         double *B, int64_t ldb, double *Sb, int64_t ldsb);
+
+// ---- QR (qr.hip) ---------------------------------------------------------------------------------
+struct QrBufs {
+    double *W;           // d x ldw : [B | Sb]
+    int64_t ldw;
+    double *V;           // d x NB  : Householder vectors of the current panel
+    double *red;         // panel reduction partials
+    double *tau;         // n
+    double *Yp;          // chunk partials of V^T [V | C]
+    double *Z;           // NB x ldw
+    double *T;           // NB x NB
+    double *qtb;         // n
+    double *RT;          // n x n  (R^T, row-major)
+};
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb);
+hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
+                              const double *Sb, const QrBufs &qb);
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status);
+hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
+                            int32_t *status);
+
+// ---- iteration (iterate.hip) ---------------------------------------------------------------------
+struct IterBufs {
+    double *part;        // P x n gradient partials
+    double *part_rr;     // P
+    double *c;           // n
+    double *xprev;       // n
+    double *RT;          // n x n (R^T row-major)
+    int32_t P;
+};
+int32_t iter_partials(int64_t m, int64_t n);
+void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt);
+hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT);
+hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
+                           const double *b, const double *x, const IterBufs &ib, double *c,
+                           double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// d = R^{-1} R^{-T} c; mode 0: write d to dout; mode 1: x += d; mode 2: x += alpha d + beta (x - xprev)
+hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
+                               const double *RT, const double *c, double *x, double *xprev,
+                               double *dout, int mode, double alpha, double beta, int32_t *status);
+hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
+                                    const double *RT, const double *y, double *x, int32_t *status);

@@ -1,0 +1,403 @@
+// Blocked Householder QR of the sketch [B | S b] (d x (n+1)) on gfx950 (Algorithm 2, third and
+// fourth lines; eq. it-sk-qr; sketch-and-solve start eq. sketched_ls).
+//
+// Panels of kNB columns.  Inside a panel the reflectors are computed one column per launch
+// (k_panel_step): every work-group owns kRB consecutive rows held in registers; each launch
+// (1) reduces, in a fixed order, the partial sums the previous launch left for this column,
+// (2) forms the reflector H = I - tau v v^T with beta = -sign(alpha) ||column||, sign(0) = +1,
+// (3) applies it to the rest of the panel, and (4) leaves the partial sums for the next column.
+// No grid-wide barrier and no spin-wait: launch boundaries order the steps.
+//
+// After the panel, the compact-WY form Q_p = I - V T V^T (T upper triangular) is built and the
+// trailing columns -- including the S b column, so Q is never formed -- are updated as
+// C <- C - V (T^T (V^T C)).  Both products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64); V^T C is split over row chunks whose partial products are summed in a
+// fixed order, so the factorization is deterministic.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kNB = 32;     // panel width
+constexpr int kRB = 256;    // rows per work-group in the panel kernels
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Panel step for column k = p0 + jc (jc = -1: no reflector yet, only the partial sums for the
+// panel's first column).  red_in/piv_in hold what the previous launch left for column k:
+//   red_in[w * kNB + l] = sum over rows of w (rows >= k) of W[i,k] W[i,p0+l]
+//   piv_in[l]           = W[k, p0+l] (the pivot row, before this step)
+// The launch writes the same quantities for column k+1 into red_out/piv_out.
+__global__ void __launch_bounds__(kRB)
+k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict__ W, int64_t ldw,
+             double *__restrict__ V, const double *__restrict__ red_in,
+             const double *__restrict__ piv_in, double *__restrict__ red_out,
+             double *__restrict__ piv_out, double *__restrict__ tau, int32_t *__restrict__ status)
+{
+    __shared__ double s_tl[kNB];
+    __shared__ double s_f[kNB];
+    __shared__ double s_part[kRB / 64][kNB];
+    __shared__ double s_scal[2];                  // beta, v_k
+    const int tid = threadIdx.x;
+    const int64_t k = p0 + jc;
+    const int64_t i = p0 + (int64_t)blockIdx.x * kRB + tid;   // this thread's row
+    const bool row_ok = i < d;
+
+    double w[kNB];
+#pragma unroll
+    for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nbp) ? W[i * ldw + p0 + l] : 0.0;
+
+    if (jc >= 0) {
+        if (tid < kNB) {
+            double acc = 0.0;
+            for (int g = 0; g < nwg; ++g) acc += red_in[g * kNB + tid];
+            s_tl[tid] = acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double alpha = piv_in[jc];
+            const double ss = s_tl[jc];
+            const double sigma = sqrt(ss);
+            double beta, t;
+            if (sigma == 0.0) {               // exactly zero column: no reflection
+                beta = 0.0;
+                t = 0.0;
+                atomicOr(status, ST_RANK);
+            } else {
+                beta = (alpha >= 0.0) ? -sigma : sigma;
+                t = 1.0 / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
+            }
+            if (!isfinite(sigma) || !isfinite(alpha)) atomicOr(status, ST_NONFINITE);
+            s_scal[0] = beta;
+            s_scal[1] = alpha - beta;
+            if (blockIdx.x == 0) tau[k] = t;
+            for (int l = 0; l < kNB; ++l)
+                s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * piv_in[l]) : 0.0;
+        }
+        __syncthreads();
+        if (row_ok) {
+            double *vrow = V + (i - p0) * kNB;
+            if (i >= k) {
+                double wjc = 0.0;
+#pragma unroll
+                for (int l = 0; l < kNB; ++l)
+                    if (l == jc) wjc = w[l];
+                const double vi = (i == k) ? s_scal[1] : wjc;
+#pragma unroll
+                for (int l = 0; l < kNB; ++l)
+                    if (l > jc && l < nbp) w[l] -= s_f[l] * vi;
+                vrow[jc] = vi;
+#pragma unroll
+                for (int l = 0; l < kNB; ++l)
+                    if (l == jc) w[l] = (i == k) ? s_scal[0] : 0.0;
+#pragma unroll
+                for (int l = 0; l < kNB; ++l)
+                    if (l >= jc && l < nbp) W[i * ldw + p0 + l] = w[l];
+            } else {
+                vrow[jc] = 0.0;
+            }
+        }
+    } else if (row_ok) {
+        double *vrow = V + (i - p0) * kNB;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) vrow[l] = 0.0;
+    }
+
+    // Partial sums for column k+1 over rows >= k+1, and its pivot row.
+    const int jn = jc + 1;
+    if (jn < nbp) {
+        const bool part = row_ok && i >= k + 1;
+        double wn = 0.0;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l)
+            if (l == jn && part) wn = w[l];
+        const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) {
+            const double v = wave_sum((l >= jn && l < nbp) ? wn * w[l] : 0.0);
+            if (lane == 0) s_part[wave][l] = v;
+        }
+        if (i == k + 1) {
+#pragma unroll
+            for (int l = 0; l < kNB; ++l) piv_out[l] = w[l];
+        }
+        __syncthreads();
+        if (tid < kNB) {
+            double acc = 0.0;
+#pragma unroll
+            for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
+            red_out[blockIdx.x * kNB + tid] = acc;
+        }
+    }
+}
+
+// out[ch][a][c] = sum over rows r of chunk ch of V[r][a] X[r][c]  (a < kNB, c < ncx).
+// Work-group tile: kNB x 64 columns; wave w computes columns 16w..16w+15 for both 16-row halves.
+// MFMA 16x16x4 f64 operand layout: A[i][kk] from lane i + 16 kk, B[kk][j] from lane j + 16 kk,
+// D[4 (lane/16) + q][lane % 16] in element q of the lane's accumulator.
+__global__ void __launch_bounds__(256)
+k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
+              const double *__restrict__ X, int64_t ldx, int64_t ncx, int64_t ldo,
+              double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t ch = blockIdx.x;
+    const int64_t r_lo = ch * chunk;
+    const int64_t r_hi = (r_lo + chunk < rows) ? r_lo + chunk : rows;
+    const int64_t col = (int64_t)blockIdx.y * 64 + 16 * wave + (lane & 15);
+    const bool col_ok = col < ncx;
+    const int kk = lane >> 4, ii = lane & 15;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r_lo; r < r_hi; r += 4) {
+        const int64_t rr = r + kk;
+        const bool ok = rr < r_hi;
+        const double a0 = ok ? V[rr * kNB + ii] : 0.0;
+        const double a1 = ok ? V[rr * kNB + 16 + ii] : 0.0;
+        const double bb = (ok && col_ok) ? X[rr * ldx + col] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, acc1, 0, 0, 0);
+    }
+    if (col_ok) {
+        double *o = out + ch * (int64_t)kNB * ldo + col;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = 4 * (lane >> 4) + q;
+            o[(int64_t)a * ldo] = acc0[q];
+            o[(int64_t)(16 + a) * ldo] = acc1[q];
+        }
+    }
+}
+
+// T of the compact-WY form: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+__global__ void __launch_bounds__(256)
+k_form_t(int nch, int64_t ldo, const double *__restrict__ Gp, const double *__restrict__ tau,
+         int64_t p0, int nbp, double *__restrict__ T)
+{
+    __shared__ double G[kNB][kNB + 1];
+    __shared__ double Ts[kNB][kNB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kNB * kNB; e += blockDim.x) {
+        const int a = e / kNB, c = e % kNB;
+        double acc = 0.0;
+        for (int g = 0; g < nch; ++g) acc += Gp[(int64_t)g * kNB * ldo + (int64_t)a * ldo + c];
+        G[a][c] = acc;
+        Ts[a][c] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nbp; ++j) {
+        const double tj = tau[p0 + j];
+        if (tid < j) {
+            double acc = 0.0;
+            for (int q = tid; q < j; ++q) acc += Ts[tid][q] * G[q][j];
+            Ts[tid][j] = -tj * acc;
+        }
+        if (tid == 0) Ts[j][j] = tj;
+        __syncthreads();
+    }
+    for (int e = tid; e < kNB * kNB; e += blockDim.x) T[e] = Ts[e / kNB][e % kNB];
+}
+
+// Z[:, c] = T^T (sum over chunks of Yp[:, :, c]) for every trailing column c.
+__global__ void __launch_bounds__(256)
+k_apply_t(int nch, int64_t ldo, const double *__restrict__ Yp, const double *__restrict__ T,
+          int64_t nc, double *__restrict__ Z, int64_t ldz)
+{
+    __shared__ double Ts[kNB * kNB];
+    for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) Ts[e] = T[e];
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double y[kNB];
+#pragma unroll
+    for (int a = 0; a < kNB; ++a) y[a] = 0.0;
+    for (int g = 0; g < nch; ++g) {
+        const double *p = Yp + (int64_t)g * kNB * ldo + c;
+#pragma unroll
+        for (int a = 0; a < kNB; ++a) y[a] += p[(int64_t)a * ldo];
+    }
+#pragma unroll
+    for (int a = 0; a < kNB; ++a) {
+        double z = 0.0;
+#pragma unroll
+        for (int b2 = 0; b2 <= a; ++b2) z += Ts[b2 * kNB + a] * y[b2];
+        Z[(int64_t)a * ldz + c] = z;
+    }
+}
+
+// C[r][c] -= sum_a V[r][a] Z[a][c] over rows r < rows, columns c < nc.
+// Work-group tile 64 x 64: wave w owns rows 16w..16w+15 and four 16-column MFMA blocks.
+__global__ void __launch_bounds__(256)
+k_update_c(int64_t rows, int64_t nc, const double *__restrict__ V, const double *__restrict__ Z,
+           int64_t ldz, double *__restrict__ C, int64_t ldc)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * wave;
+    const int64_t c0 = (int64_t)blockIdx.y * 64;
+    const int kk = lane >> 4, ii = lane & 15;
+    const int64_t ra = r0 + ii;
+    const bool ra_ok = ra < rows;
+    v4d acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < kNB; a += 4) {
+        const double av = ra_ok ? V[ra * kNB + a + kk] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int64_t cc = c0 + 16 * cb + ii;
+            const double bv = (cc < nc) ? Z[(int64_t)(a + kk) * ldz + cc] : 0.0;
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int64_t cc = c0 + 16 * cb + ii;
+        if (cc >= nc) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = r0 + 4 * kk + q;
+            if (r < rows) C[r * ldc + cc] -= acc[cb][q];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_copy_sketch(int64_t d, int64_t n, const double *__restrict__ B, int64_t ldb,
+              const double *__restrict__ Sb, double *__restrict__ W, int64_t ldw)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = n + 1;
+    if (e >= d * w) return;
+    const int64_t i = e / w, c = e % w;
+    W[i * ldw + c] = (c < n) ? B[i * ldb + c] : Sb[i];
+}
+
+// R (upper triangle of W), R^T, Q^T Sb; flags NaN/Inf.
+__global__ void __launch_bounds__(256)
+k_extract_r(int64_t n, const double *__restrict__ W, int64_t ldw, double *__restrict__ R,
+            int64_t ldr, double *__restrict__ RT, double *__restrict__ qtb,
+            int32_t *__restrict__ status)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int64_t i = e / n, c = e % n;
+    const double v = (c >= i) ? W[i * ldw + c] : 0.0;
+    if (R) R[i * ldr + c] = v;
+    RT[c * n + i] = v;
+    if (c == 0) {
+        const double q = W[i * ldw + n];
+        qtb[i] = q;
+        if (!isfinite(q)) atomicOr(status, ST_NONFINITE);
+    }
+    if (!isfinite(v)) atomicOr(status, ST_NONFINITE);
+}
+
+// Rank test on diag(R): |R_kk| <= n u max_j |R_jj|.
+__global__ void __launch_bounds__(256)
+k_rank_check(int64_t n, const double *__restrict__ RT, int32_t *__restrict__ status)
+{
+    __shared__ double smax[4];
+    double mx = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) mx = fmax(mx, fabs(RT[k * n + k]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+    const double tol = (double)n * 0x1p-53 * mx;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+        if (!(fabs(RT[k * n + k]) > tol)) atomicOr(status, ST_RANK);
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t panel_wgs_max(int64_t d) { return ceil_div(d, kRB); }
+
+int64_t chunk_rows(int64_t rows)
+{
+    int64_t ch = ceil_div(rows, 64);
+    if (ch < 256) ch = 256;
+    return ceil_div(ch, 4) * 4;
+}
+
+}  // namespace
+
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb)
+{
+    qb.ldw = ceil_div(n + 1, 8) * 8;
+    qb.W = ar.take<double>((size_t)d * (size_t)qb.ldw);
+    qb.V = ar.take<double>((size_t)d * kNB);
+    qb.red = ar.take<double>((size_t)2 * (size_t)(panel_wgs_max(d) * kNB + kNB));
+    qb.tau = ar.take<double>((size_t)n);
+    // every panel uses at most min(64, ceil(rows/256)) chunks (see chunk_rows)
+    const int64_t nch = std::min<int64_t>(64, ceil_div(d, 256));
+    const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
+    qb.Yp = ar.take<double>((size_t)nch * kNB * (size_t)ldo);
+    qb.Z = ar.take<double>((size_t)kNB * (size_t)qb.ldw);
+    qb.T = ar.take<double>((size_t)kNB * kNB);
+    qb.qtb = ar.take<double>((size_t)n);
+    qb.RT = ar.take<double>((size_t)n * (size_t)n);
+}
+
+hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
+                              const double *Sb, const QrBufs &qb)
+{
+    const int64_t total = d * (n + 1);
+    hipLaunchKernelGGL(k_copy_sketch, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, d, n,
+                       B, ldb, Sb, qb.W, qb.ldw);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status)
+{
+    const int64_t ldw = qb.ldw;
+    const int64_t red_stride = panel_wgs_max(d) * kNB + kNB;
+    double *redA = qb.red, *redB = qb.red + red_stride;
+    for (int64_t p0 = 0; p0 < n; p0 += kNB) {
+        const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
+        const int64_t rows = d - p0;
+        const int nwg = (int)ceil_div(rows, kRB);
+        double *rin = redA, *rout = redB;
+        for (int jc = -1; jc < nbp; ++jc) {
+            hipLaunchKernelGGL(k_panel_step, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
+                               ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                               rout + (int64_t)nwg * kNB, qb.tau, status);
+            double *t = rin;
+            rin = rout;
+            rout = t;
+        }
+        const int64_t c_first = p0 + nbp;
+        const int64_t nc = n + 1 - c_first;            // trailing columns incl. S b (>= 1)
+        const int64_t chunk = chunk_rows(rows);
+        const int nch = (int)ceil_div(rows, chunk);
+        const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
+        hipLaunchKernelGGL(k_vtx_partial, dim3(nch, 1), dim3(256), 0, s, rows, chunk, qb.V,
+                           (const double *)qb.V, (int64_t)kNB, (int64_t)kNB, ldo, qb.Yp);
+        hipLaunchKernelGGL(k_form_t, dim3(1), dim3(256), 0, s, nch, ldo, qb.Yp, qb.tau, p0, nbp, qb.T);
+        const double *C0 = qb.W + p0 * ldw + c_first;
+        hipLaunchKernelGGL(k_vtx_partial, dim3(nch, (unsigned)ceil_div(nc, 64)), dim3(256), 0, s,
+                           rows, chunk, qb.V, C0, ldw, nc, ldo, qb.Yp);
+        hipLaunchKernelGGL(k_apply_t, dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, s, nch, ldo,
+                           qb.Yp, qb.T, nc, qb.Z, ldw);
+        hipLaunchKernelGGL(k_update_c, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
+                           dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
+                            int32_t *status)
+{
+    hipLaunchKernelGGL(k_extract_r, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, qb.W,
+                       qb.ldw, R, ldr, qb.RT, qb.qtb, status);
+    hipLaunchKernelGGL(k_rank_check, dim3(1), dim3(256), 0, s, n, qb.RT, status);
+    return hipGetLastError();
+}

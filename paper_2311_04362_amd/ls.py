@@ -1,0 +1,220 @@
+"""ctypes binding of libls (include/ls.h): argument marshalling only.
+
+Every function takes torch tensors that live on the context's GPU and passes their device
+pointers, leading dimensions and the current torch stream to the C ABI; all arithmetic runs in the
+HIP kernels.  A missing libls.so is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libls.so")
+
+LS_OK, LS_ERR_ARG, LS_ERR_ALLOC, LS_ERR_DEVICE, LS_ERR_RANK, LS_ERR_NONFINITE, \
+    LS_ERR_DIVERGED, LS_ERR_UNSUPPORTED = range(8)
+STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_RANK",
+                "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED"]
+OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE = 1, 2, 3, 4, 5, 6, 7
+
+EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_option",
+           "ls_get_option", "ls_sketch_embedding", "ls_sketch_csr", "ls_sketch", "ls_qr_sketch",
+           "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile"]
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u64 = ctypes.c_uint64
+_f64 = ctypes.c_double
+
+
+class LSError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{where}: {name}: {detail}")
+
+
+def load():
+    """Load libls.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libls.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "ls_create": ([ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "ls_destroy": ([_vp], None),
+        "ls_last_error": ([_vp], ctypes.c_char_p),
+        "ls_limits": ([ctypes.POINTER(_i32), ctypes.POINTER(_i32)], ctypes.c_int),
+        "ls_set_option": ([_vp, ctypes.c_int, _i64, _f64], ctypes.c_int),
+        "ls_get_option": ([_vp, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(_f64)], ctypes.c_int),
+        "ls_sketch_embedding": ([_vp, _vp, _i64, _i64, _i32, _u64, _vp, _vp], ctypes.c_int),
+        "ls_sketch_csr": ([_vp, _vp, _i64, _i64, _i32, _u64, _vp, _vp], ctypes.c_int),
+        "ls_sketch": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _u64, _vp, _i64, _vp], ctypes.c_int),
+        "ls_qr_sketch": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp], ctypes.c_int),
+        "ls_gradient": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "ls_precond_solve": ([_vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
+        "ls_iterate": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp], ctypes.c_int),
+        "ls_solve": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _vp], ctypes.c_int),
+        "ls_sync": ([_vp, _vp], ctypes.c_int),
+        "ls_profile": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64), _i32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _mat(t: torch.Tensor, name: str, dtype=torch.float64):
+    if t.dim() != 2 or t.dtype != dtype or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError(f"{name}: need a 2-D {dtype} CUDA tensor with unit column stride")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _vec(t: torch.Tensor, name: str, dtype=torch.float64):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor")
+    return t
+
+
+class Context:
+    """One libls context bound to a GPU (device >= 0) or host-only (device = -1)."""
+
+    def __init__(self, device: int = 0):
+        self._L = load()
+        h = _vp()
+        st = self._L.ls_create(device, ctypes.byref(h))
+        if st != LS_OK:
+            raise LSError(st, "ls_create", f"device {device}")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.ls_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, where: str):
+        if st != LS_OK:
+            raise LSError(st, where, self._L.ls_last_error(self.h).decode())
+
+    def _stream(self):
+        return _vp(torch.cuda.current_stream().cuda_stream) if self.device >= 0 else _vp(0)
+
+    # options
+    def set_option(self, key: int, ival: int = 0, dval: float = 0.0):
+        self._check(self._L.ls_set_option(self.h, key, ival, dval), "ls_set_option")
+
+    def get_option(self, key: int):
+        iv, dv = _i64(), _f64()
+        self._check(self._L.ls_get_option(self.h, key, ctypes.byref(iv), ctypes.byref(dv)), "ls_get_option")
+        return iv.value, dv.value
+
+    # (a1) the embedding's nonzeros
+    def sketch_embedding(self, m: int, d: int, zeta: int, seed: int):
+        rows = torch.empty((m, zeta), dtype=torch.int32, device="cuda")
+        signs = torch.empty((m, zeta), dtype=torch.int8, device="cuda")
+        self._check(self._L.ls_sketch_embedding(self.h, self._stream(), m, d, zeta, seed,
+                                                _ptr(rows), _ptr(signs)), "ls_sketch_embedding")
+        return rows, signs
+
+    # (a2) compressed rows of S
+    def sketch_csr(self, m: int, d: int, zeta: int, seed: int):
+        rowptr = torch.empty(d + 1, dtype=torch.int32, device="cuda")
+        cols = torch.empty(m * zeta, dtype=torch.int32, device="cuda")
+        self._check(self._L.ls_sketch_csr(self.h, self._stream(), m, d, zeta, seed, _ptr(rowptr),
+                                          _ptr(cols)), "ls_sketch_csr")
+        return rowptr, cols
+
+    # (a3) B = S A, S b
+    def sketch(self, A: torch.Tensor, b, d: int, zeta: int, seed: int, B=None, Sb=None):
+        m, n, lda = _mat(A, "A")
+        if B is None:
+            B = torch.empty((d, n), dtype=torch.float64, device=A.device)
+        _, _, ldb = _mat(B, "B")
+        if b is not None and Sb is None:
+            Sb = torch.empty(d, dtype=torch.float64, device=A.device)
+        self._check(self._L.ls_sketch(self.h, self._stream(), m, n, _ptr(A), lda,
+                                      _ptr(None if b is None else _vec(b, "b")), d, zeta, seed,
+                                      _ptr(B), ldb, _ptr(Sb)), "ls_sketch")
+        return B, Sb
+
+    # (a4, a5) QR of [B | Sb], R and x0
+    def qr_sketch(self, B: torch.Tensor, Sb: torch.Tensor, want_x0: bool = True):
+        d, n, ldb = _mat(B, "B")
+        R = torch.empty((n, n), dtype=torch.float64, device=B.device)
+        x0 = torch.empty(n, dtype=torch.float64, device=B.device) if want_x0 else None
+        self._check(self._L.ls_qr_sketch(self.h, self._stream(), d, n, _ptr(B), ldb,
+                                         _ptr(_vec(Sb, "Sb")), _ptr(R), n, _ptr(x0)), "ls_qr_sketch")
+        return R, x0
+
+    # (a6, a7) c = A^T (b - A x), ||r||^2
+    def gradient(self, A: torch.Tensor, b: torch.Tensor, x: torch.Tensor):
+        m, n, lda = _mat(A, "A")
+        c = torch.empty(n, dtype=torch.float64, device=A.device)
+        rr = torch.empty(1, dtype=torch.float64, device=A.device)
+        self._check(self._L.ls_gradient(self.h, self._stream(), m, n, _ptr(A), lda, _ptr(_vec(b, "b")),
+                                        _ptr(_vec(x, "x")), _ptr(c), _ptr(rr)), "ls_gradient")
+        return c, rr
+
+    # (a8) d = R^{-1} R^{-T} c
+    def precond_solve(self, R: torch.Tensor, c: torch.Tensor):
+        n, _, ldr = _mat(R, "R")
+        d = torch.empty(n, dtype=torch.float64, device=R.device)
+        self._check(self._L.ls_precond_solve(self.h, self._stream(), n, _ptr(R), ldr,
+                                             _ptr(_vec(c, "c")), _ptr(d)), "ls_precond_solve")
+        return d
+
+    # (a6..a9) x <- x + R^{-1} R^{-T} A^T (b - A x), q times, in place
+    def iterate(self, A: torch.Tensor, b: torch.Tensor, R: torch.Tensor, x: torch.Tensor, q: int,
+                rnorm2: torch.Tensor | None = None):
+        m, n, lda = _mat(A, "A")
+        _, _, ldr = _mat(R, "R")
+        self._check(self._L.ls_iterate(self.h, self._stream(), m, n, _ptr(A), lda, _ptr(_vec(b, "b")),
+                                       _ptr(R), ldr, _ptr(_vec(x, "x")), q,
+                                       _ptr(None if rnorm2 is None else _vec(rnorm2, "rnorm2"))),
+                    "ls_iterate")
+        return x
+
+    # whole solve (Algorithm 2)
+    def solve(self, A: torch.Tensor, b: torch.Tensor, d: int, q: int, x: torch.Tensor | None = None):
+        m, n, lda = _mat(A, "A")
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=A.device)
+        self._check(self._L.ls_solve(self.h, self._stream(), m, n, _ptr(A), lda, _ptr(_vec(b, "b")),
+                                     d, q, _ptr(_vec(x, "x"))), "ls_solve")
+        return x
+
+    def sync(self):
+        self._check(self._L.ls_sync(self.h, self._stream()), "ls_sync")
+
+    def profile(self, reset: bool = True):
+        """(summed fused-pass kernel ms, launches) since the last reset (needs OPT_PROFILE = 1)."""
+        ms, cnt = _f64(), _i64()
+        self._check(self._L.ls_profile(self.h, ctypes.byref(ms), ctypes.byref(cnt), int(reset)), "ls_profile")
+        return ms.value, cnt.value
+
+
+def limits():
+    L = load()
+    z, n = _i32(), _i32()
+    L.ls_limits(ctypes.byref(z), ctypes.byref(n))
+    return z.value, n.value
