@@ -36,7 +36,7 @@ def pass_bytes(m: int, n: int) -> int:
 
 
 def source_digest() -> str:
-    p = os.path.join(ROOT, "paper_2311_04362_amd", "csrc", "iterate.hip")
+    p = os.path.join(ROOT, "paper_2311_04362_amd", "csrc", "pass.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
@@ -47,7 +47,7 @@ def measured_traffic():
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("iterate_hip_sha256_16") != source_digest():
+    if rec.get("pass_hip_sha256_16") != source_digest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--workload", default="ls_fp64_m2e6_n500", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=500_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build",
@@ -161,6 +163,22 @@ def main():
         "forward_error": fe,
         "pass_share_of_step": pass_ms / max((t1 - t0) * 1e3, 1e-9),
     }
+    if args.calib_copy:
+        src = torch.full((1 << 28,), 1.0, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)               # elementwise kernel: reads and writes 2 GiB each
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        moved = 2 * src.numel() * 8
+        rec["copy_calibration"] = {"bytes_read_per_copy": src.numel() * 8,
+                                   "bytes_written_per_copy": src.numel() * 8,
+                                   "ms_per_copy": ms, "GB/s": moved / (ms * 1e-3) / 1e9}
+        del src, dst
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_rows)

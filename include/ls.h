@@ -66,7 +66,9 @@ enum {
     LS_OPT_ALPHA = 4,       /* alpha of the damping/momentum update (dval; <= 0: from eps)      */
     LS_OPT_BETA = 5,        /* beta of the momentum update (dval; < 0: from eps)                */
     LS_OPT_PRECISION = 6,   /* 0: FP64 throughout; 1: sketch, QR and R-solves in FP32           */
-    LS_OPT_PROFILE = 7      /* 1: time every launch of the fused pass kernel with HIP events    */
+    LS_OPT_PROFILE = 7,     /* 1: time every launch of the fused pass kernel with HIP events    */
+    LS_OPT_QR_PANEL = 8     /* 0: one cooperative launch per QR panel when the device allows it;
+                               1: one launch per column (the fallback path)                     */
 };
 ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval);
 ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval);

@@ -269,6 +269,10 @@ ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval)
         if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "profile must be 0 or 1");
         ctx->profile = (int32_t)ival;
         return LS_OK;
+    case LS_OPT_QR_PANEL:
+        if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "QR panel mode must be 0 or 1");
+        ctx->qr_panel = (int32_t)ival;
+        return LS_OK;
     default: return ls_fail(ctx, LS_ERR_ARG, "unknown option key");
     }
 }
@@ -286,6 +290,7 @@ ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval)
     case LS_OPT_BETA: dv = ctx->beta; break;
     case LS_OPT_PRECISION: iv = ctx->precision; break;
     case LS_OPT_PROFILE: iv = ctx->profile; break;
+    case LS_OPT_QR_PANEL: iv = ctx->qr_panel; break;
     default: return LS_ERR_ARG;
     }
     if (ival) *ival = iv;
@@ -366,7 +371,7 @@ ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const do
     QrBufs qb{};
     LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb); }));
     HIP_TRY(ctx, launch_copy_sketch(s, d, n, B, ldb, Sb, qb), "copy sketch");
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status), "QR kernels");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, ldr, ctx->status), "extract R");
     if (x0) HIP_TRY(ctx, launch_back_substitution(s, n, R, ldr, qb.RT, qb.qtb, x0, ctx->status), "x0 solve");
     return LS_OK;
@@ -477,7 +482,7 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     const double scale = 1.0 / std::sqrt((double)zeta);
     HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
     // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status), "QR kernels");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
     // (c) q refinement steps.
@@ -508,6 +513,7 @@ ls_status ls_sync(ls_ctx *ctx, void *stream)
         if (st & ST_RANK) return ls_fail(ctx, LS_ERR_RANK, "R is numerically singular (rank-deficient A or sketch)");
         if (st & ST_NONFINITE) return ls_fail(ctx, LS_ERR_NONFINITE, "NaN or Inf in B, R or x");
         if (st & ST_DIVERGED) return ls_fail(ctx, LS_ERR_DIVERGED, "the residual grew without bound");
+        if (st & ST_TIMEOUT) return ls_fail(ctx, LS_ERR_DEVICE, "a grid barrier timed out (results invalid)");
     }
     return LS_OK;
 }

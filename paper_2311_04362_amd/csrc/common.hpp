@@ -11,7 +11,7 @@
 #include "ls.h"
 
 // Deferred device status bits, OR-ed into the context's status word by kernels.
-enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4 };
+enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4, ST_TIMEOUT = 8 };
 
 struct ls_ctx {
     int device = -1;                // -1: host-only context (argument checks only)
@@ -23,6 +23,7 @@ struct ls_ctx {
     double beta = -1.0;             // < 0: derived from eps
     int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves)
     int32_t profile = 0;            // 1: bracket each fused-pass launch with events
+    int32_t qr_panel = 0;           // 1: force the per-column panel path
     std::vector<hipEvent_t> ev_pool; // start/end pairs, reused
     size_t ev_used = 0;             // events recorded since the last reset (even count)
     // device memory owned by the library
@@ -46,6 +47,41 @@ struct Arena {
         return p;
     }
 };
+
+// Sum of count values p[0], p[stride], ... added in ascending order, U loads in flight at a time.
+template <int U>
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int count, int64_t stride)
+{
+    double acc = 0.0;
+    int g = 0;
+    for (; g + U <= count; g += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(g + u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    for (; g < count; ++g) acc += p[(int64_t)g * stride];
+    return acc;
+}
+
+// sum_i p[i * stride] * w[i] for i < count, accumulated in ascending i, U loads in flight.
+template <int U>
+__device__ __forceinline__ double strided_dot(const double *__restrict__ p, int64_t stride,
+                                              const double *w, int count)
+{
+    double acc = 0.0;
+    int i = 0;
+    for (; i + U <= count; i += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(i + u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u] * w[i + u];
+    }
+    for (; i < count; ++i) acc += p[(int64_t)i * stride] * w[i];
+    return acc;
+}
 
 ls_status ls_fail(ls_ctx *ctx, ls_status st, const std::string &msg);
 ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes);
@@ -81,11 +117,13 @@ struct QrBufs {
     double *T;           // NB x NB
     double *qtb;         // n
     double *RT;          // n x n  (R^T, row-major)
+    unsigned *bar;       // grid-barrier counter of the cooperative panel kernel
 };
 void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
                               const double *Sb, const QrBufs &qb);
-hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status);
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
+                     bool per_column = false);
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
                             int32_t *status);
 

@@ -1,13 +1,10 @@
-// Refinement step of iterative sketching on gfx950 (Algorithm 2 loop; eq. it-sk-it-ref; stable
-// form of Section 3.2).
+// Fused refinement pass of iterative sketching on gfx950 (Algorithm 2 loop body; stable form of
+// Section 3.2): c = A^T (b - A x) and ||b - A x||^2.
 //
-//   k_pass        fused pass over A: for each row block, r = b - A x in registers (never stored),
-//                 then acc += A^T r; each work-group writes one partial of c = A^T r and of ||r||^2.
-//                 A is read exactly once, as coalesced 64-lane segments of its rows.
-//   k_reduce      sums the partials in a fixed order (deterministic c and ||r||^2).
-//   k_solve       one work-group: R^T y = c by forward substitution, R d = y by back
-//                 substitution (64-wide diagonal blocks by one wave, off-diagonal blocks as
-//                 coalesced GEMV updates; no inverse is ever formed), then the update of x.
+//   k_pass     for each row block, r = b - A x in registers (never stored), then acc += A^T r; each
+//              work-group writes one partial of c and of ||r||^2.  A is read exactly once, as
+//              coalesced segments of its rows; the grid is one wave of co-resident work-groups.
+//   k_reduce   sums the partials in a fixed order (deterministic c and ||r||^2).
 #include "common.hpp"
 
 namespace {
@@ -107,155 +104,37 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
     }
 }
 
-// c[col] = sum_p part[p][col] in a fixed order: 4 groups of partials, each summed sequentially,
-// then the 4 group sums in order.  Work-group 0 also reduces ||r||^2.
-__global__ void __launch_bounds__(256)
+// c[col] = sum_p part[p][col] in a fixed order: 16 contiguous groups of partials, each summed in
+// ascending p, then the 16 group sums in order.  Work-group 0 also reduces ||r||^2 likewise.
+constexpr int kRedGroups = 16;
+
+__global__ void __launch_bounds__(64 * kRedGroups)
 k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__restrict__ part_rr,
          double *__restrict__ c, double *__restrict__ rr_out)
 {
-    __shared__ double s[4][64];
+    __shared__ double s[kRedGroups][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
-    const int32_t per = (P + 3) / 4;
-    const int32_t p_lo = g * per, p_hi = (p_lo + per < P) ? p_lo + per : P;
-    double acc = 0.0;
-    if (col < n)
-        for (int32_t p = p_lo; p < p_hi; ++p) acc += part[(int64_t)p * n + col];
-    s[g][lane] = acc;
+    const int32_t per = (P + kRedGroups - 1) / kRedGroups;
+    const int32_t p_lo = g * per;
+    const int32_t cnt = (p_lo + per < P) ? per : (P > p_lo ? P - p_lo : 0);
+    s[g][lane] = (col < n) ? strided_sum<8>(part + (int64_t)p_lo * n + col, cnt, n) : 0.0;
     __syncthreads();
-    if (g == 0 && col < n) c[col] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+    if (g == 0 && col < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRedGroups; ++q) t += s[q][lane];
+        c[col] = t;
+    }
     if (blockIdx.x == 0 && rr_out) {
+        __syncthreads();
+        if (lane == 0) s[g][0] = strided_sum<8>(part_rr + p_lo, cnt, 1);
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
-            for (int32_t p = 0; p < P; ++p) t += part_rr[p];
+            for (int q = 0; q < kRedGroups; ++q) t += s[q][0];
             *rr_out = t;
         }
-    }
-}
-
-// Forward substitution R^T y = v in place on s[0:n] (R upper, row-major: R^T's column i is R's
-// row i, read contiguously).  Diagonal 64-blocks by wave 0; the rest as a GEMV per block.
-__device__ void fwd_subst(int64_t n, const double *__restrict__ R, int64_t ldr, double *s)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t i0 = 0; i0 < n; i0 += 64) {
-        const int64_t i1 = (i0 + 64 < n) ? i0 + 64 : n;
-        if (wave == 0) {
-            const int64_t me = i0 + lane;
-            double v = (me < n) ? s[me] : 0.0;
-            for (int64_t i = i0; i < i1; ++i) {
-                const int li = (int)(i - i0);
-                const double yi = __shfl(v, li, 64) / R[i * ldr + i];
-                if (lane == li) v = yi;
-                else if (lane > li && me < i1) v -= R[i * ldr + me] * yi;
-            }
-            if (me < i1) s[me] = v;
-        }
-        __syncthreads();
-        for (int64_t j = i1 + tid; j < n; j += blockDim.x) {
-            double acc = 0.0;
-            for (int64_t i = i0; i < i1; ++i) acc += R[i * ldr + j] * s[i];
-            s[j] -= acc;
-        }
-        __syncthreads();
-    }
-}
-
-// Back substitution R z = v in place on s[0:n], using RT = R^T (row-major) so that column i of R
-// is read contiguously.
-__device__ void back_subst(int64_t n, const double *__restrict__ R, int64_t ldr,
-                           const double *__restrict__ RT, double *s)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t nb = (n + 63) / 64;
-    for (int64_t blk = nb - 1; blk >= 0; --blk) {
-        const int64_t i0 = blk * 64;
-        const int64_t i1 = (i0 + 64 < n) ? i0 + 64 : n;
-        if (wave == 0) {
-            const int64_t me = i0 + lane;
-            double v = (me < i1) ? s[me] : 0.0;
-            for (int64_t i = i1 - 1; i >= i0; --i) {
-                const int li = (int)(i - i0);
-                const double zi = __shfl(v, li, 64) / R[i * ldr + i];
-                if (lane == li) v = zi;
-                else if (lane < li) v -= RT[i * n + me] * zi;
-            }
-            if (me < i1) s[me] = v;
-        }
-        __syncthreads();
-        for (int64_t j = tid; j < i0; j += blockDim.x) {
-            double acc = 0.0;
-            for (int64_t i = i0; i < i1; ++i) acc += RT[i * n + j] * s[i];
-            s[j] -= acc;
-        }
-        __syncthreads();
-    }
-}
-
-// d = R^{-1} (R^{-T} c), then the update selected by mode (see launch_solve_update).
-__global__ void __launch_bounds__(1024)
-k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
-        const double *__restrict__ c, double *__restrict__ x, double *__restrict__ xprev,
-        double *__restrict__ dout, int mode, double alpha, double beta, int32_t *__restrict__ status)
-{
-    extern __shared__ double s[];
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = c[j];
-    __syncthreads();
-    fwd_subst(n, R, ldr, s);
-    back_subst(n, R, ldr, RT, s);
-    bool bad = false;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        const double dj = s[j];
-        if (mode == 0) {
-            dout[j] = dj;
-            bad |= !isfinite(dj);
-        } else if (mode == 1) {
-            const double xn = x[j] + dj;
-            x[j] = xn;
-            bad |= !isfinite(xn);
-        } else {
-            const double xo = x[j];
-            const double xn = xo + alpha * dj + beta * (xo - xprev[j]);
-            xprev[j] = xo;
-            x[j] = xn;
-            bad |= !isfinite(xn);
-        }
-    }
-    if (bad) atomicOr(status, ST_NONFINITE);
-}
-
-// x = R^{-1} y (sketch-and-solve start).
-__global__ void __launch_bounds__(1024)
-k_back(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
-       const double *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
-{
-    extern __shared__ double s[];
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = y[j];
-    __syncthreads();
-    back_subst(n, R, ldr, RT, s);
-    bool bad = false;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        x[j] = s[j];
-        bad |= !isfinite(s[j]);
-    }
-    if (bad) atomicOr(status, ST_NONFINITE);
-}
-
-__global__ void __launch_bounds__(256)
-k_transpose(int64_t n, const double *__restrict__ R, int64_t ldr, double *__restrict__ RT)
-{
-    __shared__ double tile[32][33];
-    const int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int r = ty; r < 32; r += 8) {
-        const int64_t i = by + r, j = bx + tx;
-        tile[r][tx] = (i < n && j < n) ? ((j >= i) ? R[i * ldr + j] : 0.0) : 0.0;
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int64_t i = bx + r, j = by + tx;     // RT[i][j] = R[j][i]
-        if (i < n && j < n) RT[i * n + j] = tile[tx][r];
     }
 }
 
@@ -333,13 +212,6 @@ void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt)
     ib.RT = need_rt ? ar.take<double>((size_t)n * (size_t)n) : nullptr;
 }
 
-hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT)
-{
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)),
-                       dim3(256), 0, s, n, R, ldr, RT);
-    return hipGetLastError();
-}
-
 hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, const double *x, const IterBufs &ib, double *c,
                            double *rnorm2, hipEvent_t ev0, hipEvent_t ev1)
@@ -366,24 +238,8 @@ hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A,
         e = hipEventRecord(ev1, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, s, P, n, ib.part,
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)ceil_div(n, 64)), dim3(64 * kRedGroups), 0, s, P, n, ib.part,
                        ib.part_rr, c, rnorm2);
     return hipGetLastError();
 }
 
-hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
-                               const double *RT, const double *c, double *x, double *xprev,
-                               double *dout, int mode, double alpha, double beta, int32_t *status)
-{
-    hipLaunchKernelGGL(k_solve, dim3(1), dim3(1024), (size_t)n * sizeof(double), s, n, R, ldr, RT, c,
-                       x, xprev, dout, mode, alpha, beta, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
-                                    const double *RT, const double *y, double *x, int32_t *status)
-{
-    hipLaunchKernelGGL(k_back, dim3(1), dim3(1024), (size_t)n * sizeof(double), s, n, R, ldr, RT, y,
-                       x, status);
-    return hipGetLastError();
-}

@@ -44,6 +44,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
 {
     __shared__ double s_tl[kNB];
     __shared__ double s_f[kNB];
+    __shared__ double s_red[kRB / kNB][kNB];
     __shared__ double s_part[kRB / 64][kNB];
     __shared__ double s_scal[2];                  // beta, v_k
     const int tid = threadIdx.x;
@@ -56,10 +57,20 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
     for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nbp) ? W[i * ldw + p0 + l] : 0.0;
 
     if (jc >= 0) {
-        if (tid < kNB) {
-            double acc = 0.0;
-            for (int g = 0; g < nwg; ++g) acc += red_in[g * kNB + tid];
-            s_tl[tid] = acc;
+        {   // reduce the partials: 8 contiguous groups of work-groups, then the groups in order
+            constexpr int NS = kRB / kNB;
+            const int l = tid % kNB, sl = tid / kNB;
+            const int per = (nwg + NS - 1) / NS;
+            const int g0 = sl * per;
+            const int cnt = (g0 + per < nwg) ? per : (nwg > g0 ? nwg - g0 : 0);
+            s_red[sl][l] = strided_sum<8>(red_in + (int64_t)g0 * kNB + l, cnt, kNB);
+            __syncthreads();
+            if (tid < kNB) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) acc += s_red[q][tid];
+                s_tl[tid] = acc;
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -139,10 +150,183 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
     }
 }
 
+// ---- Cooperative panel: one launch factors all kNB columns of a panel --------------------------
+// Each work-group keeps RPT * kRB rows of the panel in registers for the whole panel; a column step
+// is local arithmetic plus one grid-wide reduction of kNB partial sums.  All work-groups are
+// co-resident (cooperative launch), and each grid barrier spins a bounded number of times: if the
+// bound is ever reached the kernel flags ST_TIMEOUT and runs to completion, so it always exits.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void grid_barrier(unsigned *count, unsigned target, int32_t *status)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(count, 1u);
+        unsigned spins = 0;
+        while (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                atomicOr(status, ST_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(kRB)
+k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, int64_t ldw,
+             double *__restrict__ V, double *__restrict__ red, double *__restrict__ tau,
+             unsigned *__restrict__ bar, int32_t *__restrict__ status)
+{
+    __shared__ double s_tl[kNB];
+    __shared__ double s_f[kNB];
+    __shared__ double s_part[kRB / 64][kNB];
+    __shared__ double s_red[kRB / kNB][kNB];
+    __shared__ double s_scal[2];
+    __shared__ double s_piv[kNB];
+    __shared__ int s_haspiv;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
+    int64_t row[RPT];
+    bool ok[RPT];
+    double w[RPT][kNB];
+    double vv[RPT][kNB];                                    // Householder vectors, row by row
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * kRB + tid;
+        ok[r] = row[r] < d;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) {
+            w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : 0.0;
+            vv[r][l] = 0.0;
+        }
+    }
+    for (int jc = 0; jc < nbp; ++jc) {
+        const int64_t k = p0 + jc;
+        const int pb = jc & 1;
+        double *rb = red + (int64_t)pb * nwg * kNB;
+        // (1) partial sums of column jc over my rows >= k, and the pivot row
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                double wj = 0.0;
+#pragma unroll
+                for (int q = 0; q < kNB; ++q)
+                    if (q == jc) wj = w[r][q];
+                if (ok[r] && row[r] >= k && l >= jc && l < nbp) acc += wj * w[r][l];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) s_part[wave][l] = acc;
+        }
+        if (tid == 0) s_haspiv = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (row[r] == k) {
+#pragma unroll
+                for (int l = 0; l < kNB; ++l) s_piv[l] = w[r][l];
+                s_haspiv = 1;
+            }
+        __syncthreads();
+        // wave 0 publishes the partials (and the pivot row, from its owner): the barrier's release
+        // fence, issued by thread 0, then covers every store the other work-groups will read
+        if (tid < kNB) {
+            double acc = 0.0;
+#pragma unroll
+            for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
+            rb[(int64_t)blockIdx.x * kNB + tid] = acc;
+            if (s_haspiv) piv[pb * kNB + tid] = s_piv[tid];
+        }
+        grid_barrier(bar, (unsigned)(jc + 1) * (unsigned)nwg, status);
+        // (2) every work-group reduces the partials in the same fixed order
+        {
+            constexpr int NS = kRB / kNB;
+            const int l = tid % kNB, sl = tid / kNB;
+            const int per = (nwg + NS - 1) / NS;
+            const int g0 = sl * per;
+            const int cnt = (g0 + per < nwg) ? per : (nwg > g0 ? nwg - g0 : 0);
+            s_red[sl][l] = strided_sum<8>(rb + (int64_t)g0 * kNB + l, cnt, kNB);
+            if (tid < kNB) s_piv[tid] = piv[pb * kNB + tid];
+            __syncthreads();
+            if (tid < kNB) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) acc += s_red[q][tid];
+                s_tl[tid] = acc;
+            }
+            __syncthreads();
+        }
+        // (3) reflector H = I - tau v v^T, beta = -sign(alpha) sigma (every one of the first kNB
+        // threads forms the same scalars), then the update coefficients of the panel columns
+        if (tid < kNB) {
+            const double alpha = s_piv[jc];
+            const double sigma = sqrt(s_tl[jc]);
+            double beta, t;
+            if (sigma == 0.0) {
+                beta = 0.0;
+                t = 0.0;
+            } else {
+                beta = (alpha >= 0.0) ? -sigma : sigma;
+                t = 1.0 / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
+            }
+            const int l = tid;
+            s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * s_piv[l]) : 0.0;
+            if (tid == 0) {
+                if (sigma == 0.0) atomicOr(status, ST_RANK);
+                if (!isfinite(sigma) || !isfinite(alpha)) atomicOr(status, ST_NONFINITE);
+                s_scal[0] = beta;
+                s_scal[1] = alpha - beta;
+                if (blockIdx.x == 0) tau[k] = t;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (!ok[r] || row[r] < k) continue;
+            double wjc = 0.0;
+#pragma unroll
+            for (int q = 0; q < kNB; ++q)
+                if (q == jc) wjc = w[r][q];
+            const double vi = (row[r] == k) ? s_scal[1] : wjc;
+#pragma unroll
+            for (int l = 0; l < kNB; ++l)
+                if (l > jc && l < nbp) w[r][l] -= s_f[l] * vi;
+#pragma unroll
+            for (int l = 0; l < kNB; ++l)
+                if (l == jc) {
+                    vv[r][l] = vi;
+                    w[r][l] = (row[r] == k) ? s_scal[0] : 0.0;
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        if (!ok[r]) continue;
+        double *vrow = V + (row[r] - p0) * kNB;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) {
+            if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
+            vrow[l] = vv[r][l];
+        }
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 // out[ch][a][c] = sum over rows r of chunk ch of V[r][a] X[r][c]  (a < kNB, c < ncx).
 // Work-group tile: kNB x 64 columns; wave w computes columns 16w..16w+15 for both 16-row halves.
-// MFMA 16x16x4 f64 operand layout: A[i][kk] from lane i + 16 kk, B[kk][j] from lane j + 16 kk,
-// D[4 (lane/16) + q][lane % 16] in element q of the lane's accumulator.
+// MFMA 16x16x4 f64 operand layout (checked on gfx950): A[i][kk] from lane i + 16 kk, B[kk][j] from
+// lane j + 16 kk; element q of a lane's accumulator holds D[4 q + lane/16][lane % 16].
 __global__ void __launch_bounds__(256)
 k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
               const double *__restrict__ X, int64_t ldx, int64_t ncx, int64_t ldo,
@@ -169,7 +353,7 @@ k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
         double *o = out + ch * (int64_t)kNB * ldo + col;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int a = 4 * (lane >> 4) + q;
+            const int a = 4 * q + (lane >> 4);
             o[(int64_t)a * ldo] = acc0[q];
             o[(int64_t)(16 + a) * ldo] = acc1[q];
         }
@@ -186,9 +370,7 @@ k_form_t(int nch, int64_t ldo, const double *__restrict__ Gp, const double *__re
     const int tid = threadIdx.x;
     for (int e = tid; e < kNB * kNB; e += blockDim.x) {
         const int a = e / kNB, c = e % kNB;
-        double acc = 0.0;
-        for (int g = 0; g < nch; ++g) acc += Gp[(int64_t)g * kNB * ldo + (int64_t)a * ldo + c];
-        G[a][c] = acc;
+        G[a][c] = strided_sum<8>(Gp + (int64_t)a * ldo + c, nch, (int64_t)kNB * ldo);
         Ts[a][c] = 0.0;
     }
     __syncthreads();
@@ -205,23 +387,43 @@ k_form_t(int nch, int64_t ldo, const double *__restrict__ Gp, const double *__re
     for (int e = tid; e < kNB * kNB; e += blockDim.x) T[e] = Ts[e / kNB][e % kNB];
 }
 
-// Z[:, c] = T^T (sum over chunks of Yp[:, :, c]) for every trailing column c.
-__global__ void __launch_bounds__(256)
+// Z[:, c] = T^T (sum over chunks of Yp[:, :, c]) for every trailing column c.  Four threads per
+// column each sum a contiguous quarter of the chunks; the quarters are added in order.
+constexpr int kApplyCols = 32;
+constexpr int kApplySlices = 4;
+
+__global__ void __launch_bounds__(kApplyCols * kApplySlices)
 k_apply_t(int nch, int64_t ldo, const double *__restrict__ Yp, const double *__restrict__ T,
           int64_t nc, double *__restrict__ Z, int64_t ldz)
 {
     __shared__ double Ts[kNB * kNB];
+    __shared__ double ys[kApplySlices][kNB][kApplyCols + 1];
     for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) Ts[e] = T[e];
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    const int cl = threadIdx.x % kApplyCols, sl = threadIdx.x / kApplyCols;
+    const int64_t c = (int64_t)blockIdx.x * kApplyCols + cl;
+    const int per = (nch + kApplySlices - 1) / kApplySlices;
+    const int g0 = sl * per;
+    const int cnt = (g0 + per < nch) ? per : (nch > g0 ? nch - g0 : 0);
     double y[kNB];
 #pragma unroll
     for (int a = 0; a < kNB; ++a) y[a] = 0.0;
-    for (int g = 0; g < nch; ++g) {
-        const double *p = Yp + (int64_t)g * kNB * ldo + c;
+    if (c < nc) {
+        for (int g = g0; g < g0 + cnt; ++g) {
+            const double *p = Yp + (int64_t)g * kNB * ldo + c;
 #pragma unroll
-        for (int a = 0; a < kNB; ++a) y[a] += p[(int64_t)a * ldo];
+            for (int a = 0; a < kNB; ++a) y[a] += p[(int64_t)a * ldo];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < kNB; ++a) ys[sl][a][cl] = y[a];
+    __syncthreads();
+    if (sl != 0 || c >= nc) return;
+#pragma unroll
+    for (int a = 0; a < kNB; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kApplySlices; ++q) t += ys[q][a][cl];
+        y[a] = t;
     }
 #pragma unroll
     for (int a = 0; a < kNB; ++a) {
@@ -263,7 +465,7 @@ k_update_c(int64_t rows, int64_t nc, const double *__restrict__ V, const double 
         if (cc >= nc) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t r = r0 + 4 * kk + q;
+            const int64_t r = r0 + 4 * q + kk;
             if (r < rows) C[r * ldc + cc] -= acc[cb][q];
         }
     }
@@ -345,6 +547,7 @@ void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb)
     qb.T = ar.take<double>((size_t)kNB * kNB);
     qb.qtb = ar.take<double>((size_t)n);
     qb.RT = ar.take<double>((size_t)n * (size_t)n);
+    qb.bar = ar.take<unsigned>(64);
 }
 
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
@@ -356,7 +559,65 @@ hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status)
+namespace {
+
+// Work-groups of k_panel_coop<RPT> that can be co-resident on the current device (0: cooperative
+// launch unavailable).  Cached per device.
+template <int RPT>
+int coop_capacity()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cache[dev] != 0) return cache[dev] > 0 ? cache[dev] : 0;
+    int coop = 0, cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<RPT>), kRB, 0) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        cache[dev] = -1;
+        return 0;
+    }
+    cache[dev] = cus * per_cu;
+    return cache[dev];
+}
+
+template <int RPT>
+hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, double *W,
+                             int64_t ldw, double *V, double *red, double *tau, unsigned *bar,
+                             int32_t *status)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bar, 64);
+    void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &status};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<RPT>), dim3(nwg),
+                                      dim3(kRB), args, 0, s);
+}
+
+// One panel by the cooperative kernel if the device can hold its grid; returns false to request
+// the per-column path.
+bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufs &qb,
+                       int32_t *status, hipError_t &err)
+{
+    const int64_t rows = d - p0;
+    err = hipSuccess;
+    int nwg = (int)ceil_div(rows, kRB);
+    if (nwg <= coop_capacity<1>()) {
+        err = launch_panel_coop<1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
+        return true;
+    }
+    nwg = (int)ceil_div(rows, 2 * kRB);
+    if (nwg <= coop_capacity<2>()) {
+        err = launch_panel_coop<2>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
+        return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
+                     bool per_column)
 {
     const int64_t ldw = qb.ldw;
     const int64_t red_stride = panel_wgs_max(d) * kNB + kNB;
@@ -364,16 +625,20 @@ hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int3
     for (int64_t p0 = 0; p0 < n; p0 += kNB) {
         const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
         const int64_t rows = d - p0;
-        const int nwg = (int)ceil_div(rows, kRB);
-        double *rin = redA, *rout = redB;
-        for (int jc = -1; jc < nbp; ++jc) {
-            hipLaunchKernelGGL(k_panel_step, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
-                               ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
-                               rout + (int64_t)nwg * kNB, qb.tau, status);
-            double *t = rin;
-            rin = rout;
-            rout = t;
+        hipError_t err = hipSuccess;
+        if (per_column || !panel_cooperative(s, d, p0, nbp, qb, status, err)) {
+            const int nwg = (int)ceil_div(rows, kRB);
+            double *rin = redA, *rout = redB;
+            for (int jc = -1; jc < nbp; ++jc) {
+                hipLaunchKernelGGL(k_panel_step, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
+                                   ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                                   rout + (int64_t)nwg * kNB, qb.tau, status);
+                double *t = rin;
+                rin = rout;
+                rout = t;
+            }
         }
+        if (err != hipSuccess) return err;
         const int64_t c_first = p0 + nbp;
         const int64_t nc = n + 1 - c_first;            // trailing columns incl. S b (>= 1)
         const int64_t chunk = chunk_rows(rows);
@@ -385,7 +650,7 @@ hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int3
         const double *C0 = qb.W + p0 * ldw + c_first;
         hipLaunchKernelGGL(k_vtx_partial, dim3(nch, (unsigned)ceil_div(nc, 64)), dim3(256), 0, s,
                            rows, chunk, qb.V, C0, ldw, nc, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_apply_t, dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, s, nch, ldo,
+        hipLaunchKernelGGL(k_apply_t, dim3((unsigned)ceil_div(nc, kApplyCols)), dim3(kApplyCols * kApplySlices), 0, s, nch, ldo,
                            qb.Yp, qb.T, nc, qb.Z, ldw);
         hipLaunchKernelGGL(k_update_c, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
                            dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);

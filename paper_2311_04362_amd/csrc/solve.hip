@@ -1,0 +1,280 @@
+// Triangular solves and update of iterative sketching on gfx950 (Algorithm 2: d_i = R^{-1} (R^{-T} c_i),
+// x_{i+1} = x_i + d_i; the damping / momentum update of eq. damping_momentum; the sketch-and-solve
+// start x_0 = R^{-1} (Q^T S b)).
+//
+//   k_solve       one work-group: R^T y = c by forward substitution, R d = y by back substitution
+//                 (32-wide diagonal blocks by one wave while the other waves apply earlier blocks
+//                 as coalesced GEMV updates; no inverse matrix is ever formed), then the update.
+//   k_back        back substitution alone (x_0).
+//   k_transpose   R^T for the column reads of the back substitution.
+#include "common.hpp"
+
+namespace {
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xFFFFFFFFull), l);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+constexpr int kSB = 32;                 // diagonal block of the substitutions
+
+// LDS of the substitution kernels: double-buffered diagonal block, the reciprocals of its diagonal,
+// and the block of R that couples the current block of unknowns to the next one.
+struct SubstLds {
+    double diag[2][kSB][kSB + 1];
+    double rdiag[2][kSB];
+    double off[2][kSB][kSB + 1];
+};
+
+// dst = R[r0:r0+kSB, c0:c0+kSB] (zero outside the n x n matrix), read by threads t.. of the WG.
+__device__ __forceinline__ void load_block(double (*dst)[kSB + 1], const double *__restrict__ R,
+                                           int64_t ldr, int64_t n, int64_t r0, int64_t c0, int t,
+                                           int nt)
+{
+    for (int e = t; e < kSB * kSB; e += nt) {
+        const int r = e / kSB, c = e % kSB;
+        const int64_t gr = r0 + r, gc = c0 + c;
+        dst[r][c] = (gr >= 0 && gr < n && gc >= 0 && gc < n) ? R[gr * ldr + gc] : 0.0;
+    }
+}
+
+// Reciprocals of R[i0+l, i0+l] (1 outside R), by threads t.. of the WG.
+__device__ __forceinline__ void load_rdiag(double *dst, const double *__restrict__ R, int64_t ldr,
+                                           int64_t n, int64_t i0, int t, int nt)
+{
+    for (int l = t; l < kSB; l += nt) {
+        const int64_t g = i0 + l;
+        dst[l] = (g >= 0 && g < n) ? 1.0 / R[g * ldr + g] : 1.0;
+    }
+}
+
+// Solves one diagonal block in wave 0: lane l holds unknown l (v) and column l of the block
+// (colv[li] = T[li][l] of the triangular factor being applied, T = R^T forward or R backward);
+// unknown li = v_li * (1 / T[li][li]) is broadcast with readlane and removed from the others.
+template <bool kForward>
+__device__ __forceinline__ double block_solve(double v, const double (*diag)[kSB + 1],
+                                              const double *rdiag, int nb, int lane)
+{
+    const int lc = (lane < kSB) ? lane : 0;
+    const double rd = rdiag[lc];
+#define colv(li) (kForward ? diag[li][lc] : diag[lc][li])
+    if (kForward) {
+#pragma unroll
+        for (int li = 0; li < kSB; ++li) {
+            if (li < nb) {
+                const double yi = readlane_f64(v * rd, li);
+                if (lane == li) v = yi;
+                else if (lane > li && lane < nb) v -= colv(li) * yi;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int li = kSB - 1; li >= 0; --li) {
+            if (li < nb) {
+                const double zi = readlane_f64(v * rd, li);
+                if (lane == li) v = zi;
+                else if (lane < li) v -= colv(li) * zi;
+            }
+        }
+    }
+#undef colv
+    return v;
+}
+
+// Forward substitution R^T y = v in place on s[0:n] (R upper triangular, row-major).
+// Block k of unknowns is solved by wave 0 alone (block_solve); wave 0 then forms the contribution
+// of block k to block k+1 in registers (the "carry").  Meanwhile waves 1.. apply block k-1 to every
+// unknown past block k+1 (coalesced reads of rows of R, 32 loads in flight per thread) and load the
+// next diagonal, reciprocal and coupling blocks into the other LDS buffer.  Each unknown therefore
+// receives the terms of earlier blocks in a fixed order, and no two waves write one entry in one
+// phase.  Unknowns are divided by R_ii as multiplication by the rounded reciprocal.
+__device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ R, int64_t ldr, double *s, SubstLds &L)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (int)((n + kSB - 1) / kSB);
+    load_block(L.diag[0], R, ldr, n, 0, 0, tid, blockDim.x);
+    load_rdiag(L.rdiag[0], R, ldr, n, 0, tid, blockDim.x);
+    load_block(L.off[0], R, ldr, n, 0, kSB, tid, blockDim.x);
+    __syncthreads();
+    double carry = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        const int64_t i0 = (int64_t)k * kSB;
+        const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
+        const int buf = k & 1;
+        double next = 0.0;
+        if (wave == 0) {
+            double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
+            v = block_solve<true>(v, L.diag[buf], L.rdiag[buf], nb, lane);
+            if (lane < nb) s[i0 + lane] = v;
+            if (k + 1 < nblk) {
+                const int lc = (lane < kSB) ? lane : 0;
+#pragma unroll
+                for (int li = 0; li < kSB; ++li)
+                    if (li < nb) next += L.off[buf][li][lc] * readlane_f64(v, li);
+            }
+        } else {
+            const int t = tid - 64, nt = blockDim.x - 64;
+            if (k >= 1) {                               // block k-1 (always full) -> past block k+1
+                const int64_t p0 = i0 - kSB;
+                for (int64_t j = i0 + kSB + t; j < n; j += nt)
+                    s[j] -= strided_dot<kSB>(R + p0 * ldr + j, ldr, s + p0, kSB);
+            }
+            if (k + 1 < nblk) {
+                load_block(L.diag[buf ^ 1], R, ldr, n, i0 + kSB, i0 + kSB, t, nt);
+                load_rdiag(L.rdiag[buf ^ 1], R, ldr, n, i0 + kSB, t, nt);
+                load_block(L.off[buf ^ 1], R, ldr, n, i0 + kSB, i0 + 2 * kSB, t, nt);
+            }
+        }
+        __syncthreads();
+        carry = next;
+    }
+}
+
+// Back substitution R z = v in place on s[0:n]; RT = R^T (row-major, ld n) gives the columns of R
+// contiguously for the far updates.  Same schedule as fwd_subst, blocks taken from the last.
+__device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__ R, int64_t ldr,
+                           const double *__restrict__ RT, double *s, SubstLds &L)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (int)((n + kSB - 1) / kSB);
+    const int64_t last0 = (int64_t)(nblk - 1) * kSB;
+    load_block(L.diag[0], R, ldr, n, last0, last0, tid, blockDim.x);
+    load_rdiag(L.rdiag[0], R, ldr, n, last0, tid, blockDim.x);
+    load_block(L.off[0], R, ldr, n, last0 - kSB, last0, tid, blockDim.x);  // rows of block B-1
+    __syncthreads();
+    double carry = 0.0;
+    for (int t = 0; t < nblk; ++t) {
+        const int B = nblk - 1 - t;
+        const int64_t i0 = (int64_t)B * kSB;
+        const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
+        const int buf = t & 1;
+        double next = 0.0;
+        if (wave == 0) {
+            double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
+            v = block_solve<false>(v, L.diag[buf], L.rdiag[buf], nb, lane);
+            if (lane < nb) s[i0 + lane] = v;
+            if (B >= 1) {
+                const int lc = (lane < kSB) ? lane : 0;
+#pragma unroll
+                for (int li = 0; li < kSB; ++li)
+                    if (li < nb) next += L.off[buf][lc][li] * readlane_f64(v, li);
+            }
+        } else {
+            const int th = tid - 64, nt = blockDim.x - 64;
+            if (t >= 1) {                               // block B+1 -> blocks B-1, B-2, ...
+                const int64_t p0 = i0 + kSB;
+                const int pb = (int)((p0 + kSB < n) ? kSB : n - p0);
+                for (int64_t j = th; j < i0; j += nt)
+                    s[j] -= strided_dot<kSB>(RT + p0 * n + j, n, s + p0, pb);
+            }
+            if (B >= 1) {
+                load_block(L.diag[buf ^ 1], R, ldr, n, i0 - kSB, i0 - kSB, th, nt);
+                load_rdiag(L.rdiag[buf ^ 1], R, ldr, n, i0 - kSB, th, nt);
+                load_block(L.off[buf ^ 1], R, ldr, n, i0 - 2 * kSB, i0 - kSB, th, nt);
+            }
+        }
+        __syncthreads();
+        carry = next;
+    }
+}
+
+// d = R^{-1} (R^{-T} c), then the update selected by mode (see launch_solve_update).
+constexpr int kSolveThreads = 1024;
+
+__global__ void __launch_bounds__(kSolveThreads)
+k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
+        const double *__restrict__ c, double *__restrict__ x, double *__restrict__ xprev,
+        double *__restrict__ dout, int mode, double alpha, double beta, int32_t *__restrict__ status)
+{
+    extern __shared__ double s[];
+    __shared__ SubstLds L;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = c[j];
+    __syncthreads();
+    fwd_subst(n, R, ldr, s, L);
+    back_subst(n, R, ldr, RT, s, L);
+    bool bad = false;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const double dj = s[j];
+        if (mode == 0) {
+            dout[j] = dj;
+            bad |= !isfinite(dj);
+        } else if (mode == 1) {
+            const double xn = x[j] + dj;
+            x[j] = xn;
+            bad |= !isfinite(xn);
+        } else {
+            const double xo = x[j];
+            const double xn = xo + alpha * dj + beta * (xo - xprev[j]);
+            xprev[j] = xo;
+            x[j] = xn;
+            bad |= !isfinite(xn);
+        }
+    }
+    if (bad) atomicOr(status, ST_NONFINITE);
+}
+
+// x = R^{-1} y (sketch-and-solve start).
+__global__ void __launch_bounds__(kSolveThreads)
+k_back(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
+       const double *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
+{
+    extern __shared__ double s[];
+    __shared__ SubstLds L;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = y[j];
+    __syncthreads();
+    back_subst(n, R, ldr, RT, s, L);
+    bool bad = false;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        x[j] = s[j];
+        bad |= !isfinite(s[j]);
+    }
+    if (bad) atomicOr(status, ST_NONFINITE);
+}
+
+__global__ void __launch_bounds__(256)
+k_transpose(int64_t n, const double *__restrict__ R, int64_t ldr, double *__restrict__ RT)
+{
+    __shared__ double tile[32][33];
+    const int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = by + r, j = bx + tx;
+        tile[r][tx] = (i < n && j < n) ? ((j >= i) ? R[i * ldr + j] : 0.0) : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bx + r, j = by + tx;     // RT[i][j] = R[j][i]
+        if (i < n && j < n) RT[i * n + j] = tile[tx][r];
+    }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT)
+{
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)),
+                       dim3(256), 0, s, n, R, ldr, RT);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
+                               const double *RT, const double *c, double *x, double *xprev,
+                               double *dout, int mode, double alpha, double beta, int32_t *status)
+{
+    hipLaunchKernelGGL(k_solve, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, c,
+                       x, xprev, dout, mode, alpha, beta, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
+                                    const double *RT, const double *y, double *x, int32_t *status)
+{
+    hipLaunchKernelGGL(k_back, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, y,
+                       x, status);
+    return hipGetLastError();
+}

@@ -18,7 +18,8 @@ LS_OK, LS_ERR_ARG, LS_ERR_ALLOC, LS_ERR_DEVICE, LS_ERR_RANK, LS_ERR_NONFINITE, \
     LS_ERR_DIVERGED, LS_ERR_UNSUPPORTED = range(8)
 STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_RANK",
                 "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED"]
-OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE = 1, 2, 3, 4, 5, 6, 7
+OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL = \
+    1, 2, 3, 4, 5, 6, 7, 8
 
 EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_option",
            "ls_get_option", "ls_sketch_embedding", "ls_sketch_csr", "ls_sketch", "ls_qr_sketch",

@@ -122,17 +122,33 @@ def _check_qr(ctx, B, Sb, kappa_hint):
     assert np.linalg.norm(x0 - xo) <= tol + 1e-300
 
 
+@pytest.mark.parametrize("panel", [0, 1])     # cooperative panel, per-column launches
 @pytest.mark.parametrize("d,n,kappa", [(1, 1, 1.0), (20, 1, 1.0), (100, 31, 1e2), (100, 32, 1e2),
                                        (200, 33, 1e2), (1000, 50, 1e3), (2000, 100, 1e6),
-                                       (5000, 257, 1e2), (10000, 500, 1e4)])
-def test_qr_sketch_vs_oracle(ctx, d, n, kappa):
+                                       (5000, 257, 1e2), (10000, 500, 1e4), (70000, 40, 1e3)])
+def test_qr_sketch_vs_oracle(ctx, d, n, kappa, panel):
     rng = np.random.default_rng(d * 7 + n)
     Uq, _ = np.linalg.qr(rng.standard_normal((d, n)))
     Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
     sig = kappa ** (-np.arange(n) / max(n - 1, 1))
     B = (Uq * sig) @ Vq.T
     Sb = rng.standard_normal(d)
-    _check_qr(ctx, B, Sb, kappa)
+    ctx.set_option(ls.OPT_QR_PANEL, panel)
+    try:
+        _check_qr(ctx, B, Sb, kappa)
+    finally:
+        ctx.set_option(ls.OPT_QR_PANEL, 0)
+
+
+def test_qr_panel_paths_agree_bitwise(ctx):
+    """Both panel implementations do the same arithmetic in the same order."""
+    rng = np.random.default_rng(3)
+    B, Sb = dev(rng.standard_normal((3000, 70))), dev(rng.standard_normal(3000))
+    R0, x0 = ctx.qr_sketch(B, Sb)
+    ctx.set_option(ls.OPT_QR_PANEL, 1)
+    R1, x1 = ctx.qr_sketch(B, Sb)
+    ctx.set_option(ls.OPT_QR_PANEL, 0)
+    assert torch.equal(R0, R1) and torch.equal(x0, x1)
 
 
 def test_qr_of_real_sketch_ill_conditioned(ctx):
@@ -191,7 +207,10 @@ def test_gradient_float_bound(ctx, n, m):
     # |c_hat - c| <= gamma_{n+1} |A|^T (|b| + |A||x|) + gamma_m |A|^T |r| for each side (Higham 3.5)
     bound = (n + 2) * U * (aA.T @ (np.abs(b) + aA @ np.abs(x))) + (m + 1) * U * (aA.T @ np.abs(r))
     assert np.all(np.abs(host(c) - ec) <= 2 * bound)
-    assert abs(host(rr)[0] - err) <= 1e-10 * err + 1e-300
+    # each r_i is within e_i = gamma_{n+1} (|b_i| + |A_i| |x|) on either side
+    e = (n + 2) * U * (np.abs(b) + aA @ np.abs(x))
+    rr_bound = 2 * (2 * np.abs(r) @ e + e @ e) + 2 * (m + 1) * U * (r @ r)
+    assert abs(host(rr)[0] - err) <= rr_bound
 
 
 # ---------------------------------------------------------------- (a8, a9) solves, update
@@ -339,3 +358,50 @@ def test_device_argument_errors(ctx):
     with pytest.raises(ls.LSError) as e:
         ctx.solve(A, torch.zeros(10, dtype=torch.float64, device="cuda"), 2, 3)   # d < n
     assert e.value.status == ls.LS_ERR_ARG
+
+
+# --------------------------------------------------------- damping / momentum (Section 6)
+
+@pytest.mark.parametrize("update", [1, 2])
+def test_iterate_damping_momentum_matches_oracle(ctx, update):
+    p = make_problem_cpu(ProblemSpec(m=4000, n=50, kappa=1e3, beta=1e-3, d=1000, seed=6))
+    n, d, q = 50, 1000, 12
+    eps2 = n / d
+    alpha = (1 - eps2) ** 2 / (1 + eps2) if update == 1 else (1 - eps2) ** 2
+    beta = 0.0 if update == 1 else eps2
+    xq, xh = oracle.iterative_sketching_dm(p.A, p.b, n, d, q, alpha, beta, seed=p.spec.sketch_seed)
+    _, _, R, _ = oracle.iterative_sketching(p.A, p.b, n, d, 0, seed=p.spec.sketch_seed, history=True)
+    ctx.set_option(ls.OPT_UPDATE, update)
+    ctx.set_option(ls.OPT_ALPHA, 0, alpha)
+    ctx.set_option(ls.OPT_BETA, 0, beta)
+    try:
+        x = dev(xh[0])
+        ctx.iterate(dev(p.A)[:, :n], dev(p.b), dev(R), x, q)
+        ctx.sync()
+    finally:
+        ctx.set_option(ls.OPT_UPDATE, 0)
+        ctx.set_option(ls.OPT_ALPHA, 0, 0.0)
+        ctx.set_option(ls.OPT_BETA, 0, -1.0)
+    assert np.linalg.norm(host(x) - xq) <= 1e-10 * np.linalg.norm(xq)
+
+
+def test_solve_momentum_converges_faster(ctx):
+    """Theorem 6.1: momentum contracts at about eps = sqrt(n/d) per step, plain at about 2 eps."""
+    spec = ProblemSpec(m=4000, n=50, kappa=1e6, beta=1e-3, d=1000, seed=7)
+    p = make_problem_cpu(spec)
+    A, b = dev(p.A)[:, :50], dev(p.b)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    fe_hh = np.linalg.norm(oracle.householder_lstsq(p.Aview, p.b)[0] - p.x_true)
+    x_plain = host(ctx.solve(A, b, 1000, 12))
+    ctx.set_option(ls.OPT_UPDATE, 2)
+    try:
+        x_mom = host(ctx.solve(A, b, 1000, 12))
+        x_mom40 = host(ctx.solve(A, b, 1000, 40))
+    finally:
+        ctx.set_option(ls.OPT_UPDATE, 0)
+    e_plain = np.linalg.norm(x_plain - p.x_true)
+    e_mom = np.linalg.norm(x_mom - p.x_true)
+    assert e_mom < e_plain
+    assert np.linalg.norm(x_mom40 - p.x_true) <= 10 * fe_hh
+    xo, _ = oracle.iterative_sketching_dm(p.A, p.b, 50, 1000, 12, (1 - 0.05) ** 2, 0.05, seed=spec.sketch_seed)
+    assert np.linalg.norm(x_mom - xo) <= 1e-6 * np.linalg.norm(xo) + 10 * fe_hh
