@@ -23,17 +23,19 @@ __device__ __forceinline__ double group_sum(double v)
 
 // G lanes share one row; a wave holds 64/G rows at once and RT such row groups per tile.
 // Lane sub (= lane % G) owns columns sub + G*c, c < CPL, so each load instruction of a row group
-// reads G consecutive doubles.
+// reads G consecutive doubles.  Tiles are dealt round-robin over all waves of the grid, so at any
+// moment the grid streams one contiguous window of A; A and b are read with non-temporal loads
+// (each byte is used once, so they need not displace anything in the caches).
 template <int G, int CPL, int RT>
 __global__ void __launch_bounds__(kPassThreads)
 k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
-       const double *__restrict__ x, int64_t rows_per_wg, double *__restrict__ part,
-       double *__restrict__ part_rr)
+       const double *__restrict__ x, double *__restrict__ part, double *__restrict__ part_rr)
 {
     constexpr int RPW = 64 / G;
     constexpr int TILE = RPW * RT;                   // rows per wave per tile
+    constexpr int WAVES = kPassThreads / 64;
     __shared__ double s_acc[64 * CPL];
-    __shared__ double s_rr[kPassThreads / 64];
+    __shared__ double s_rr[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane % G, grp = lane / G;
 
@@ -50,19 +52,19 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
     for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
     double rr = 0.0;
 
-    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
-    const int64_t r_end = (r_begin + rows_per_wg < m) ? r_begin + rows_per_wg : m;
-    for (int64_t t0 = r_begin + (int64_t)wave * TILE; t0 < r_end; t0 += (int64_t)(kPassThreads / 64) * TILE) {
+    const int64_t step = (int64_t)gridDim.x * WAVES * TILE;
+    for (int64_t t0 = ((int64_t)blockIdx.x * WAVES + wave) * TILE; t0 < m; t0 += step) {
         double a[RT][CPL];
         double bb[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int64_t row = t0 + (int64_t)t * RPW + grp;
-            const bool rok = row < r_end;
+            const bool rok = row < m;
             const double *ar = A + row * lda + sub;
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) a[t][c] = (rok && cok[c]) ? ar[G * c] : 0.0;
-            bb[t] = rok ? b[row] : 0.0;
+            for (int c = 0; c < CPL; ++c)
+                a[t][c] = (rok && cok[c]) ? __builtin_nontemporal_load(ar + G * c) : 0.0;
+            bb[t] = rok ? __builtin_nontemporal_load(b + row) : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -86,7 +88,7 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
     for (int off = 1; off < 64; off <<= 1) rr += __shfl_xor(rr, off, 64);
     if (lane == 0) s_rr[wave] = rr;
 #pragma unroll
-    for (int w = 0; w < kPassThreads / 64; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
         if (wave == w && grp == 0) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c)
@@ -99,7 +101,7 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
     if (threadIdx.x == 0) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kPassThreads / 64; ++w) s += s_rr[w];
+        for (int w = 0; w < WAVES; ++w) s += s_rr[w];
         part_rr[blockIdx.x] = s;
     }
 }
@@ -181,18 +183,18 @@ int resident_wgs(int id, const void *fn)
 }
 
 template <int G, int CPL, int RT>
-void pass_launch(hipStream_t s, int P, int64_t rows_per_wg, int64_t m, int64_t n, const double *A,
-                 int64_t lda, const double *b, const double *x, double *part, double *part_rr)
+void pass_launch(hipStream_t s, int P, int64_t m, int64_t n, const double *A, int64_t lda,
+                 const double *b, const double *x, double *part, double *part_rr)
 {
     hipLaunchKernelGGL((k_pass<G, CPL, RT>), dim3(P), dim3(kPassThreads), 0, s, m, n, A, lda, b, x,
-                       rows_per_wg, part, part_rr);
+                       part, part_rr);
 }
 
 }  // namespace
 
 int32_t iter_partials(int64_t m, int64_t n)
 {
-    // One wave of co-resident work-groups, each over a contiguous block of at least 256 rows.
+    // One wave of co-resident work-groups (at most one per 256 rows).
     const PassVariant v = pass_variant(n);
     int64_t P = resident_wgs(v.id, v.fn);
     if (P > kMaxPartials) P = kMaxPartials;
@@ -217,20 +219,19 @@ hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A,
                            double *rnorm2, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int P = ib.P;
-    const int64_t rpw = ceil_div(m, P);
     if (ev0) {
         hipError_t e0 = hipEventRecord(ev0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (n <= 8) pass_launch<8, 1, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 16) pass_launch<16, 1, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 32) pass_launch<16, 2, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 64) pass_launch<16, 4, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 128) pass_launch<64, 2, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 256) pass_launch<64, 4, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 512) pass_launch<64, 8, 4>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 1024) pass_launch<64, 16, 2>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 2048) pass_launch<64, 32, 1>(s, P, rpw, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    if (n <= 8) pass_launch<8, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 16) pass_launch<16, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 32) pass_launch<16, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 64) pass_launch<16, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 128) pass_launch<64, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 256) pass_launch<64, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 512) pass_launch<64, 8, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 1024) pass_launch<64, 16, 2>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    else if (n <= 2048) pass_launch<64, 32, 1>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
     else return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -24,11 +24,34 @@ constexpr int kRB = 256;    // rows per work-group in the panel kernels
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double wave_sum(double v)
+
+// Sums v[0..kNB) across the 64 lanes of a wave by recursive halving: at each step a lane keeps half
+// of its values and adds the partner's copy of them, so 32 values need 16+8+4+2+1+1 exchanges.
+// On return lane l holds the wave total of value (l >> 1) & 31 (both lanes of a pair agree).
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[kNB], int lane)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int half = kNB / 2, off = 32; half >= 1; half >>= 1, off >>= 1) {
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = upper ? v[i] : v[i + half];
+            const double keep = upper ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// Value index held by lane l after wave_transpose_sum: the bits of l above bit 0, reversed over
+// the five halving steps (the step with partner offset 32 decides the highest index bit).
+__device__ __forceinline__ int transpose_sum_index(int lane)
+{
+    int idx = 0;
+#pragma unroll
+    for (int b = 0, off = 32; off >= 2; ++b, off >>= 1)
+        if (lane & off) idx |= (kNB / 2) >> b;
+    return idx;
 }
 
 // Panel step for column k = p0 + jc (jc = -1: no reflector yet, only the partial sums for the
@@ -131,11 +154,11 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
         for (int l = 0; l < kNB; ++l)
             if (l == jn && part) wn = w[l];
         const int wave = tid >> 6, lane = tid & 63;
+        double pv[kNB];
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) {
-            const double v = wave_sum((l >= jn && l < nbp) ? wn * w[l] : 0.0);
-            if (lane == 0) s_part[wave][l] = v;
-        }
+        for (int l = 0; l < kNB; ++l) pv[l] = (l >= jn && l < nbp) ? wn * w[l] : 0.0;
+        const double tot = wave_transpose_sum(pv, lane);
+        if ((lane & 1) == 0) s_part[wave][transpose_sum_index(lane)] = tot;
         if (i == k + 1) {
 #pragma unroll
             for (int l = 0; l < kNB; ++l) piv_out[l] = w[l];
@@ -152,26 +175,34 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
 
 // ---- Cooperative panel: one launch factors all kNB columns of a panel --------------------------
 // Each work-group keeps RPT * kRB rows of the panel in registers for the whole panel; a column step
-// is local arithmetic plus one grid-wide reduction of kNB partial sums.  All work-groups are
+// is local arithmetic plus one grid-wide exchange of kNB partial sums.  All work-groups are
 // co-resident (cooperative launch), and each grid barrier spins a bounded number of times: if the
 // bound is ever reached the kernel flags ST_TIMEOUT and runs to completion, so it always exits.
-constexpr unsigned kSpinLimit = 1u << 22;
+constexpr unsigned kSpinLimit = 1u << 20;
 
-__device__ __forceinline__ void grid_barrier(unsigned *count, unsigned target, int32_t *status)
+// Grid barrier by per-work-group step flags: after publishing its data, work-group g stores
+// flag[g] = epoch with release semantics; the barrier waits until every flag has reached epoch.
+// Flags only grow, so they need no reset within a launch.  The wait is bounded: past kSpinLimit
+// polls the kernel flags ST_TIMEOUT and continues, so every work-group always finishes.
+__device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned epoch, int32_t *status)
 {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(count, 1u);
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        for (;;) {
+            bool mine = true;
+            for (int g = threadIdx.x; g < nwg; g += 64)
+                mine &= __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+            if (__all(mine)) break;
             if (++spins > kSpinLimit) {
-                atomicOr(status, ST_TIMEOUT);
+                if (threadIdx.x == 0) atomicOr(status, ST_TIMEOUT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -191,6 +222,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
     __shared__ int s_haspiv;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
+    const int tidx = transpose_sum_index(lane);
     int64_t row[RPT];
     bool ok[RPT];
     double w[RPT][kNB];
@@ -210,19 +242,23 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
         const int pb = jc & 1;
         double *rb = red + (int64_t)pb * nwg * kNB;
         // (1) partial sums of column jc over my rows >= k, and the pivot row
+        {
+            double pv[kNB];
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) {
-            double acc = 0.0;
+            for (int l = 0; l < kNB; ++l) pv[l] = 0.0;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 double wj = 0.0;
 #pragma unroll
                 for (int q = 0; q < kNB; ++q)
                     if (q == jc) wj = w[r][q];
-                if (ok[r] && row[r] >= k && l >= jc && l < nbp) acc += wj * w[r][l];
+                const bool use = ok[r] && row[r] >= k;
+#pragma unroll
+                for (int l = 0; l < kNB; ++l)
+                    if (use && l >= jc && l < nbp) pv[l] += wj * w[r][l];
             }
-            acc = wave_sum(acc);
-            if (lane == 0) s_part[wave][l] = acc;
+            const double tot = wave_transpose_sum(pv, lane);
+            if ((lane & 1) == 0) s_part[wave][tidx] = tot;
         }
         if (tid == 0) s_haspiv = 0;
         __syncthreads();
@@ -243,7 +279,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
             rb[(int64_t)blockIdx.x * kNB + tid] = acc;
             if (s_haspiv) piv[pb * kNB + tid] = s_piv[tid];
         }
-        grid_barrier(bar, (unsigned)(jc + 1) * (unsigned)nwg, status);
+        flag_barrier(bar, nwg, (unsigned)(jc + 1), status);
         // (2) every work-group reduces the partials in the same fixed order
         {
             constexpr int NS = kRB / kNB;
@@ -547,7 +583,7 @@ void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb)
     qb.T = ar.take<double>((size_t)kNB * kNB);
     qb.qtb = ar.take<double>((size_t)n);
     qb.RT = ar.take<double>((size_t)n * (size_t)n);
-    qb.bar = ar.take<unsigned>(64);
+    qb.bar = ar.take<unsigned>(1024);
 }
 
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
@@ -588,7 +624,7 @@ hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int 
                              int64_t ldw, double *V, double *red, double *tau, unsigned *bar,
                              int32_t *status)
 {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bar, 64);
+    hipLaunchKernelGGL(k_zero_u32, dim3((nwg + 255) / 256), dim3(256), 0, s, bar, nwg);
     void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &status};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<RPT>), dim3(nwg),
                                       dim3(kRB), args, 0, s);

@@ -7,7 +7,7 @@
 //   k_csr_sort      sorts every sketch row by column index j, making the CSR unique: ascending j.
 //   k_gather        one wave per (sketch row, 64*CPL-column tile): B[k,:] = sum of +-A[j,:] over the
 //                   row's columns in ascending j, times fl(1/sqrt(zeta)).  Rows of A are read as
-//                   coalesced 512-byte segments; no atomics on floating-point data.
+//                   coalesced 512-byte segments (non-temporal); no atomics on floating-point data.
 #include "common.hpp"
 
 namespace {
@@ -202,7 +202,7 @@ k_gather(int64_t n, int32_t ntiles, const double *__restrict__ A, int64_t lda,
         for (int u = 0; u < 4; ++u) {
             const double *row = A + (int64_t)(v[u] & 0x7FFFFFFFu) * lda + c0;
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) a[u][c] = ok[c] ? row[64 * c] : 0.0;
+            for (int c = 0; c < CPL; ++c) a[u][c] = ok[c] ? __builtin_nontemporal_load(row + 64 * c) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {

@@ -19,10 +19,12 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-constexpr int kSB = 32;                 // diagonal block of the substitutions
+// Diagonal block of the substitutions used by the library.
+constexpr int kSolveBlock = 32;
 
 // LDS of the substitution kernels: double-buffered diagonal block, the reciprocals of its diagonal,
 // and the block of R that couples the current block of unknowns to the next one.
+template <int kSB>
 struct SubstLds {
     double diag[2][kSB][kSB + 1];
     double rdiag[2][kSB];
@@ -30,6 +32,7 @@ struct SubstLds {
 };
 
 // dst = R[r0:r0+kSB, c0:c0+kSB] (zero outside the n x n matrix), read by threads t.. of the WG.
+template <int kSB>
 __device__ __forceinline__ void load_block(double (*dst)[kSB + 1], const double *__restrict__ R,
                                            int64_t ldr, int64_t n, int64_t r0, int64_t c0, int t,
                                            int nt)
@@ -42,6 +45,7 @@ __device__ __forceinline__ void load_block(double (*dst)[kSB + 1], const double 
 }
 
 // Reciprocals of R[i0+l, i0+l] (1 outside R), by threads t.. of the WG.
+template <int kSB>
 __device__ __forceinline__ void load_rdiag(double *dst, const double *__restrict__ R, int64_t ldr,
                                            int64_t n, int64_t i0, int t, int nt)
 {
@@ -54,7 +58,7 @@ __device__ __forceinline__ void load_rdiag(double *dst, const double *__restrict
 // Solves one diagonal block in wave 0: lane l holds unknown l (v) and column l of the block
 // (colv[li] = T[li][l] of the triangular factor being applied, T = R^T forward or R backward);
 // unknown li = v_li * (1 / T[li][li]) is broadcast with readlane and removed from the others.
-template <bool kForward>
+template <int kSB, bool kForward>
 __device__ __forceinline__ double block_solve(double v, const double (*diag)[kSB + 1],
                                               const double *rdiag, int nb, int lane)
 {
@@ -91,13 +95,15 @@ __device__ __forceinline__ double block_solve(double v, const double (*diag)[kSB
 // next diagonal, reciprocal and coupling blocks into the other LDS buffer.  Each unknown therefore
 // receives the terms of earlier blocks in a fixed order, and no two waves write one entry in one
 // phase.  Unknowns are divided by R_ii as multiplication by the rounded reciprocal.
-__device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ R, int64_t ldr, double *s, SubstLds &L)
+template <int kSB>
+__device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ R, int64_t ldr, double *s,
+                                          SubstLds<kSB> &L)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (int)((n + kSB - 1) / kSB);
-    load_block(L.diag[0], R, ldr, n, 0, 0, tid, blockDim.x);
-    load_rdiag(L.rdiag[0], R, ldr, n, 0, tid, blockDim.x);
-    load_block(L.off[0], R, ldr, n, 0, kSB, tid, blockDim.x);
+    load_block<kSB>(L.diag[0], R, ldr, n, 0, 0, tid, blockDim.x);
+    load_rdiag<kSB>(L.rdiag[0], R, ldr, n, 0, tid, blockDim.x);
+    load_block<kSB>(L.off[0], R, ldr, n, 0, kSB, tid, blockDim.x);
     __syncthreads();
     double carry = 0.0;
     for (int k = 0; k < nblk; ++k) {
@@ -107,7 +113,7 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ 
         double next = 0.0;
         if (wave == 0) {
             double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
-            v = block_solve<true>(v, L.diag[buf], L.rdiag[buf], nb, lane);
+            v = block_solve<kSB, true>(v, L.diag[buf], L.rdiag[buf], nb, lane);
             if (lane < nb) s[i0 + lane] = v;
             if (k + 1 < nblk) {
                 const int lc = (lane < kSB) ? lane : 0;
@@ -123,9 +129,9 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ 
                     s[j] -= strided_dot<kSB>(R + p0 * ldr + j, ldr, s + p0, kSB);
             }
             if (k + 1 < nblk) {
-                load_block(L.diag[buf ^ 1], R, ldr, n, i0 + kSB, i0 + kSB, t, nt);
-                load_rdiag(L.rdiag[buf ^ 1], R, ldr, n, i0 + kSB, t, nt);
-                load_block(L.off[buf ^ 1], R, ldr, n, i0 + kSB, i0 + 2 * kSB, t, nt);
+                load_block<kSB>(L.diag[buf ^ 1], R, ldr, n, i0 + kSB, i0 + kSB, t, nt);
+                load_rdiag<kSB>(L.rdiag[buf ^ 1], R, ldr, n, i0 + kSB, t, nt);
+                load_block<kSB>(L.off[buf ^ 1], R, ldr, n, i0 + kSB, i0 + 2 * kSB, t, nt);
             }
         }
         __syncthreads();
@@ -135,15 +141,16 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ 
 
 // Back substitution R z = v in place on s[0:n]; RT = R^T (row-major, ld n) gives the columns of R
 // contiguously for the far updates.  Same schedule as fwd_subst, blocks taken from the last.
+template <int kSB>
 __device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__ R, int64_t ldr,
-                           const double *__restrict__ RT, double *s, SubstLds &L)
+                                           const double *__restrict__ RT, double *s, SubstLds<kSB> &L)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (int)((n + kSB - 1) / kSB);
     const int64_t last0 = (int64_t)(nblk - 1) * kSB;
-    load_block(L.diag[0], R, ldr, n, last0, last0, tid, blockDim.x);
-    load_rdiag(L.rdiag[0], R, ldr, n, last0, tid, blockDim.x);
-    load_block(L.off[0], R, ldr, n, last0 - kSB, last0, tid, blockDim.x);  // rows of block B-1
+    load_block<kSB>(L.diag[0], R, ldr, n, last0, last0, tid, blockDim.x);
+    load_rdiag<kSB>(L.rdiag[0], R, ldr, n, last0, tid, blockDim.x);
+    load_block<kSB>(L.off[0], R, ldr, n, last0 - kSB, last0, tid, blockDim.x);  // rows of block B-1
     __syncthreads();
     double carry = 0.0;
     for (int t = 0; t < nblk; ++t) {
@@ -154,7 +161,7 @@ __device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__
         double next = 0.0;
         if (wave == 0) {
             double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
-            v = block_solve<false>(v, L.diag[buf], L.rdiag[buf], nb, lane);
+            v = block_solve<kSB, false>(v, L.diag[buf], L.rdiag[buf], nb, lane);
             if (lane < nb) s[i0 + lane] = v;
             if (B >= 1) {
                 const int lc = (lane < kSB) ? lane : 0;
@@ -171,9 +178,9 @@ __device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__
                     s[j] -= strided_dot<kSB>(RT + p0 * n + j, n, s + p0, pb);
             }
             if (B >= 1) {
-                load_block(L.diag[buf ^ 1], R, ldr, n, i0 - kSB, i0 - kSB, th, nt);
-                load_rdiag(L.rdiag[buf ^ 1], R, ldr, n, i0 - kSB, th, nt);
-                load_block(L.off[buf ^ 1], R, ldr, n, i0 - 2 * kSB, i0 - kSB, th, nt);
+                load_block<kSB>(L.diag[buf ^ 1], R, ldr, n, i0 - kSB, i0 - kSB, th, nt);
+                load_rdiag<kSB>(L.rdiag[buf ^ 1], R, ldr, n, i0 - kSB, th, nt);
+                load_block<kSB>(L.off[buf ^ 1], R, ldr, n, i0 - 2 * kSB, i0 - kSB, th, nt);
             }
         }
         __syncthreads();
@@ -184,17 +191,18 @@ __device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__
 // d = R^{-1} (R^{-T} c), then the update selected by mode (see launch_solve_update).
 constexpr int kSolveThreads = 1024;
 
+template <int kSB>
 __global__ void __launch_bounds__(kSolveThreads)
 k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
         const double *__restrict__ c, double *__restrict__ x, double *__restrict__ xprev,
         double *__restrict__ dout, int mode, double alpha, double beta, int32_t *__restrict__ status)
 {
     extern __shared__ double s[];
-    __shared__ SubstLds L;
+    __shared__ SubstLds<kSB> L;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = c[j];
     __syncthreads();
-    fwd_subst(n, R, ldr, s, L);
-    back_subst(n, R, ldr, RT, s, L);
+    fwd_subst<kSB>(n, R, ldr, s, L);
+    back_subst<kSB>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
         const double dj = s[j];
@@ -217,15 +225,16 @@ k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__re
 }
 
 // x = R^{-1} y (sketch-and-solve start).
+template <int kSB>
 __global__ void __launch_bounds__(kSolveThreads)
 k_back(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
        const double *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
 {
     extern __shared__ double s[];
-    __shared__ SubstLds L;
+    __shared__ SubstLds<kSB> L;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = y[j];
     __syncthreads();
-    back_subst(n, R, ldr, RT, s, L);
+    back_subst<kSB>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
         x[j] = s[j];
@@ -266,7 +275,7 @@ hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_
                                const double *RT, const double *c, double *x, double *xprev,
                                double *dout, int mode, double alpha, double beta, int32_t *status)
 {
-    hipLaunchKernelGGL(k_solve, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, c,
+    hipLaunchKernelGGL(k_solve<kSolveBlock>, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, c,
                        x, xprev, dout, mode, alpha, beta, status);
     return hipGetLastError();
 }
@@ -274,7 +283,7 @@ hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_
 hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                     const double *RT, const double *y, double *x, int32_t *status)
 {
-    hipLaunchKernelGGL(k_back, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, y,
+    hipLaunchKernelGGL(k_back<kSolveBlock>, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, y,
                        x, status);
     return hipGetLastError();
 }
