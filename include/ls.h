@@ -67,8 +67,11 @@ enum {
     LS_OPT_BETA = 5,        /* beta of the momentum update (dval; < 0: from eps)                */
     LS_OPT_PRECISION = 6,   /* 0: FP64 throughout; 1: sketch, QR and R-solves in FP32           */
     LS_OPT_PROFILE = 7,     /* 1: time every launch of the fused pass kernel with HIP events    */
-    LS_OPT_QR_PANEL = 8     /* 0: one cooperative launch per QR panel when the device allows it;
+    LS_OPT_QR_PANEL = 8,    /* 0: one cooperative launch per QR panel when the device allows it;
                                1: one launch per column (the fallback path)                     */
+    LS_OPT_STOP = 9,        /* 1: ls_solve stops by the rule of Section 3.3, q being the maximum  */
+    LS_OPT_GAMMA = 10,      /* gamma of that rule (dval, default 1)                              */
+    LS_OPT_RHO = 11         /* rho of that rule (dval, default 0.04)                             */
 };
 ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval);
 ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval);
@@ -135,11 +138,24 @@ ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doub
                      double *rnorm2);
 
 /* ---- Whole solve (Algorithm 2) ------------------------------------------------------------------
- * x (n) = x_q for A (m x n, lda), b (m), embedding dimension d (d <= 0: d = 20 n) and q steps,
- * with zeta and seed from the options.  Enqueues sketch, QR and iterations, then waits on `stream`
- * and returns the deferred status (as ls_sync).  Requires d >= n and the limits above. */
+ * x (n) = x_q for A (m x n, lda), b (m), embedding dimension d and q steps, with zeta and seed from
+ * the options.  d <= 0 selects eq. (dimension): d = max(ceil((6 + 4 sqrt 2) n exp(W((6 - 4 sqrt 2)
+ * (m / n^2) ln(1/u)))), 20 n) with u = 2^-53 and W the principal branch of Lambert's W.
+ * With LS_OPT_STOP = 1, q is the maximum number of steps and the iteration ends at the first x_i
+ * with ||r(x_i) - r(x_{i-1})|| <= u (gamma normest ||x_i|| + rho condest ||r(x_i)||) (Section 3.3);
+ * normest is ceil(ln n) steps of the power method on R from g_i = 2 u_i - 1, u_i the 53 high bits
+ * of SplitMix64 output i of the stream seed + 0x632BE59BD9B4E019 scaled to [0, 1); condest is
+ * ||R||_1 times Hager's estimate of ||R^{-1}||_1.  The decision is taken on the device; a residual
+ * that grows past 100 ||r(x_0)|| ends the iteration with LS_ERR_DIVERGED.
+ * Enqueues sketch, QR and iterations, then waits on `stream` and returns the deferred status (as
+ * ls_sync).  Requires d >= n and the limits above. */
 ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
                    const double *b, int64_t d, int32_t q, double *x);
+
+/* After ls_solve: the embedding dimension used, the number of refinement steps made, and (with
+ * LS_OPT_STOP = 1) normest and condest (NaN otherwise).  Any pointer may be NULL. */
+ls_status ls_solve_info(ls_ctx *ctx, int64_t *d_used, int32_t *steps, double *normest,
+                        double *condest);
 
 /* Waits for `stream`, then returns and clears the deferred device status of the context. */
 ls_status ls_sync(ls_ctx *ctx, void *stream);

@@ -65,6 +65,10 @@ def lib():
         L.orc_normest.argtypes = [_i64, _D, _i64, _D, _i32]
         L.orc_condest_1.restype = ctypes.c_double
         L.orc_condest_1.argtypes = [_i64, _D, _i64]
+        L.orc_iterative_sketching_stop.restype = ctypes.c_int
+        L.orc_iterative_sketching_stop.argtypes = [_i64, _i64, _D, _i64, _D, _i64, _i32, _u64, _i32,
+                                                   ctypes.c_double, ctypes.c_double, _D, _D,
+                                                   ctypes.POINTER(ctypes.c_int32), _D]
         L.orc_sketch_row.restype = None
         L.orc_sketch_row.argtypes = [_i64, _i64, _D, _i64, _I8, _i32, _D]
         L.orc_dimension.restype = ctypes.c_int64
@@ -218,3 +222,28 @@ def condest_1(R) -> float:
 
 def dimension(m: int, n: int, u: float = 2.0 ** -53) -> int:
     return int(lib().orc_dimension(m, n, u))
+
+
+def iterative_sketching_stop(A, b, n: int, d: int, qmax: int, g, zeta: int = 8, seed: int = 0,
+                             gamma: float = 1.0, rho: float = 0.04):
+    """Algorithm 2 with the Section 3.3 stopping rule: (x, iterations, normest, condest)."""
+    A, m, _, lda = _mat(A)
+    x = np.zeros(n)
+    it = ctypes.c_int32(0)
+    est = np.zeros(2)
+    rc = lib().orc_iterative_sketching_stop(m, n, _dp(A), lda, _dp(_f64(b)), d, zeta, seed, qmax,
+                                            gamma, rho, _dp(_f64(g)), _dp(x), ctypes.byref(it),
+                                            _dp(est))
+    if rc:
+        raise ValueError(f"orc_iterative_sketching_stop failed (rc={rc})")
+    return x, it.value, float(est[0]), float(est[1])
+
+
+def normest_start(n: int, seed: int):
+    """Start vector of the randomized power method: g_i uniform on [-1, 1) from SplitMix64 output
+    i of the stream seed (53 high bits), the same counter-based source as the embedding."""
+    out = np.empty(n)
+    for i in range(n):
+        z = splitmix64(seed, i)
+        out[i] = 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
+    return out

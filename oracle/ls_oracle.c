@@ -431,3 +431,64 @@ void orc_sketch_row(int64_t cnt, int64_t n, const double *rows, int64_t ldr, con
     double scale = 1.0 / sqrt((double)zeta);
     for (int64_t c = 0; c < n; ++c) out[c] *= scale;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Algorithm 2 with the stopping rule of Section 3.3: normest = orc_normest(R, g, ceil(ln n)),
+ * condest = orc_condest_1(R); after each update, stop and return x_{i+1} as soon as
+ *   ||r(x_{i+1}) - r(x_i)|| <= u (gamma normest ||x_{i+1}|| + rho condest ||r(x_{i+1})||),
+ * u = 2^-53, with at most qmax updates.  Both residual norms are evaluated from their definition
+ * (r(x) = b - A x for each iterate).  *iters receives the number of updates made; est (nullable,
+ * 2 doubles) receives normest and condest.  Return codes as orc_iterative_sketching. */
+int orc_iterative_sketching_stop(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                                 int64_t d, int32_t zeta, uint64_t seed, int32_t qmax, double gamma,
+                                 double rho, const double *g, double *x, int32_t *iters, double *est)
+{
+    if (n < 1 || m < n || d < n || qmax < 0 || lda < n) return 1;
+    const double u = ldexp(1.0, -53);
+    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)n);
+    double *Sb = (double *)malloc(sizeof(double) * (size_t)d);
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dv = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xn = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 2;
+    *iters = 0;
+    if (!B || !Sb || !R || !c || !y || !dv || !xn) goto done;
+    rc = orc_sketch(m, n, A, lda, b, d, zeta, seed, B, n, Sb);
+    if (rc) goto done;
+    rc = orc_householder_lstsq(d, n, B, n, Sb, R, n, NULL, x, NULL);
+    if (rc) goto done;
+    {
+        int32_t steps = (int32_t)ceil(log((double)n));
+        if (steps < 1) steps = 1;
+        double normest = orc_normest(n, R, n, g, steps);
+        double condest = orc_condest_1(n, R, n);
+        if (est) { est[0] = normest; est[1] = condest; }
+        for (int32_t i = 0; i < qmax; ++i) {
+            orc_residual_gradient(m, n, A, lda, b, x, c, NULL);
+            orc_solve_rt(n, R, n, c, y);
+            orc_solve_r(n, R, n, y, dv);
+            for (int64_t l = 0; l < n; ++l) xn[l] = x[l] + dv[l];
+            /* ||r(x_{i+1}) - r(x_i)|| = ||A (x_{i+1} - x_i)||, ||r(x_{i+1})||, ||x_{i+1}|| */
+            double dr = 0.0, rr = 0.0, xx = 0.0;
+            for (int64_t l = 0; l < n; ++l) xx += xn[l] * xn[l];
+            for (int64_t j = 0; j < m; ++j) {
+                double ad = 0.0, ax = 0.0;
+                for (int64_t l = 0; l < n; ++l) {
+                    ad += A[j * lda + l] * (xn[l] - x[l]);
+                    ax += A[j * lda + l] * xn[l];
+                }
+                double r = b[j] - ax;
+                dr += ad * ad;
+                rr += r * r;
+            }
+            for (int64_t l = 0; l < n; ++l) x[l] = xn[l];
+            *iters = i + 1;
+            if (sqrt(dr) <= u * (gamma * normest * sqrt(xx) + rho * condest * sqrt(rr))) break;
+        }
+    }
+done:
+    free(B); free(Sb); free(R); free(c); free(y); free(dv); free(xn);
+    return rc;
+}

@@ -126,6 +126,30 @@ ls_status timed_gradient(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const
     return LS_OK;
 }
 
+// Principal branch of Lambert's W for y >= 0 by Halley's iteration on f(w) = w e^w - y.
+double lambert_w0(double y)
+{
+    double w = std::log1p(y);
+    for (int it = 0; it < 64; ++it) {
+        const double ew = std::exp(w);
+        const double f = w * ew - y;
+        const double fp = ew * (w + 1.0);
+        const double step = f / (fp - (w + 2.0) * f / (2.0 * w + 2.0));
+        w -= step;
+        if (std::fabs(step) <= 1e-15 * (1.0 + std::fabs(w))) break;
+    }
+    return w;
+}
+
+// Embedding dimension of eq. (dimension), u = 2^-53.
+int64_t dimension_rule(int64_t m, int64_t n)
+{
+    const double a = 6.0 + 4.0 * std::sqrt(2.0), c = 6.0 - 4.0 * std::sqrt(2.0);
+    const double y = c * ((double)m / ((double)n * (double)n)) * (53.0 * std::log(2.0));
+    const int64_t d = (int64_t)std::ceil(a * (double)n * std::exp(lambert_w0(y)));
+    return d > 20 * n ? d : 20 * n;
+}
+
 void update_params(const ls_ctx *ctx, int64_t n, int64_t d, int &mode, double &alpha, double &beta)
 {
     mode = 1;
@@ -273,6 +297,18 @@ ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval)
         if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "QR panel mode must be 0 or 1");
         ctx->qr_panel = (int32_t)ival;
         return LS_OK;
+    case LS_OPT_STOP:
+        if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "stop must be 0 or 1");
+        ctx->stop = (int32_t)ival;
+        return LS_OK;
+    case LS_OPT_GAMMA:
+        if (!(dval >= 0.0) || !std::isfinite(dval)) return ls_fail(ctx, LS_ERR_ARG, "gamma must be finite and >= 0");
+        ctx->gamma = dval;
+        return LS_OK;
+    case LS_OPT_RHO:
+        if (!(dval >= 0.0) || !std::isfinite(dval)) return ls_fail(ctx, LS_ERR_ARG, "rho must be finite and >= 0");
+        ctx->rho = dval;
+        return LS_OK;
     default: return ls_fail(ctx, LS_ERR_ARG, "unknown option key");
     }
 }
@@ -291,6 +327,9 @@ ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval)
     case LS_OPT_PRECISION: iv = ctx->precision; break;
     case LS_OPT_PROFILE: iv = ctx->profile; break;
     case LS_OPT_QR_PANEL: iv = ctx->qr_panel; break;
+    case LS_OPT_STOP: iv = ctx->stop; break;
+    case LS_OPT_GAMMA: dv = ctx->gamma; break;
+    case LS_OPT_RHO: dv = ctx->rho; break;
     default: return LS_ERR_ARG;
     }
     if (ival) *ival = iv;
@@ -456,7 +495,7 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     if (!ctx) return LS_ERR_ARG;
     LS_TRY(check_n(ctx, n));
     if (m < n) return ls_fail(ctx, LS_ERR_ARG, "m must be >= n");
-    if (d <= 0) d = 20 * n;
+    if (d <= 0) d = dimension_rule(m, n);
     if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
     if (q < 0) return ls_fail(ctx, LS_ERR_ARG, "q must be >= 0");
     const int32_t zeta = ctx->zeta;
@@ -470,13 +509,18 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     SketchBufs sb{};
     QrBufs qb{};
     IterBufs ib{};
-    double *R = nullptr;
+    double *R = nullptr, *est_work = nullptr;
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
         sketch_bufs(ar, m, d, zeta, sb);
         qr_bufs(ar, d, n, qb);
         iter_bufs(ar, m, n, ib, false);
         R = ar.take<double>((size_t)n * (size_t)n);
+        est_work = ar.take<double>((size_t)3 * (size_t)n);
     }));
+    ctx->last_d = d;
+    ctx->last_q = q;
+    ctx->last_steps = q;
+    ctx->last_normest = ctx->last_condest = NAN;
     // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
     LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
@@ -485,17 +529,55 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
-    // (c) q refinement steps.
+    // (c) q refinement steps (with the stopping rule: at most q, ended on the device).
     int mode;
     double alpha, beta;
     update_params(ctx, n, d, mode, alpha, beta);
+    StopArgs st;
+    if (ctx->stop) {
+        HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+        HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
+        st.state = ib.state;
+        st.scal = ib.scal;
+        st.dx = ib.dx;
+        st.gamma = ctx->gamma;
+        st.rho = ctx->rho;
+    }
     if (mode == 2 && q > 0)
         HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
     for (int32_t i = 0; i < q; ++i) {
-        LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
-        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status), "solve kernel");
+        if (ctx->stop) {
+            st.check = (i >= 1);
+            hipEvent_t e0, e1;
+            LS_TRY(pass_events(ctx, e0, e1));
+            HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
+                                         i >= 1 ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
+        } else {
+            LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
+        }
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
     }
-    return ls_sync(ctx, stream);
+    const ls_status status = ls_sync(ctx, stream);
+    if (ctx->stop) {
+        int32_t stv[2];
+        double scv[4];
+        HIP_TRY(ctx, hipMemcpy(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost), "read steps");
+        HIP_TRY(ctx, hipMemcpy(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost), "read estimates");
+        ctx->last_steps = stv[1];
+        ctx->last_normest = scv[2];
+        ctx->last_condest = scv[3];
+    }
+    return status;
+}
+
+ls_status ls_solve_info(ls_ctx *ctx, int64_t *d_used, int32_t *steps, double *normest, double *condest)
+{
+    if (!ctx) return LS_ERR_ARG;
+    if (d_used) *d_used = ctx->last_d;
+    if (steps) *steps = ctx->last_steps;
+    if (normest) *normest = ctx->last_normest;
+    if (condest) *condest = ctx->last_condest;
+    return LS_OK;
 }
 
 ls_status ls_sync(ls_ctx *ctx, void *stream)

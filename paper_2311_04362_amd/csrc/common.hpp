@@ -24,6 +24,13 @@ struct ls_ctx {
     int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves)
     int32_t profile = 0;            // 1: bracket each fused-pass launch with events
     int32_t qr_panel = 0;           // 1: force the per-column panel path
+    int32_t stop = 0;               // 1: Section 3.3 stopping rule in ls_solve
+    double gamma = 1.0, rho = 0.04;
+    // what the last ls_solve used (for ls_solve_info)
+    int64_t last_d = 0;
+    int32_t last_q = 0;
+    int32_t last_steps = 0;         // refinement steps made
+    double last_normest = 0.0, last_condest = 0.0;
     std::vector<hipEvent_t> ev_pool; // start/end pairs, reused
     size_t ev_used = 0;             // events recorded since the last reset (even count)
     // device memory owned by the library
@@ -131,6 +138,10 @@ hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *
 struct IterBufs {
     double *part;        // P x n gradient partials
     double *part_rr;     // P
+    double *part_ad;     // P partials of ||A dx||^2 (stopping rule)
+    double *dx;          // n: x_i - x_{i-1}
+    double *scal;        // [0] ||r||^2, [1] ||A dx||^2, [2] normest, [3] condest, [4] ||r_1||^2
+    int32_t *state;      // [0] done flag, [1] updates made
     double *c;           // n
     double *xprev;       // n
     double *RT;          // n x n (R^T row-major)
@@ -141,10 +152,26 @@ void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt);
 hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT);
 hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, const double *x, const IterBufs &ib, double *c,
-                           double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                           const double *dx = nullptr, double *ad_out = nullptr,
+                           const int32_t *done = nullptr);
+// Stopping rule of Section 3.3 evaluated on the device (see k_solve).
+struct StopArgs {
+    int32_t *state = nullptr;   // [0] done flag, [1] updates made (nullptr: no stopping rule)
+    double *scal = nullptr;     // [0] ||r_i||^2, [1] ||A dx||^2, [2] normest, [3] condest, [4] ||r_0||^2
+    double *dx = nullptr;       // n: x_i - x_{i-1}, written by each update
+    double gamma = 1.0, rho = 0.04;
+    int check = 0;              // 1 when scal[1] holds ||A (x_i - x_{i-1})||^2 for this step
+};
 // d = R^{-1} R^{-T} c; mode 0: write d to dout; mode 1: x += d; mode 2: x += alpha d + beta (x - xprev)
 hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                const double *RT, const double *c, double *x, double *xprev,
-                               double *dout, int mode, double alpha, double beta, int32_t *status);
+                               double *dout, int mode, double alpha, double beta, int32_t *status,
+                               const StopArgs &st = StopArgs());
+// normest (power method from a SplitMix64 start, ceil(ln n) steps) -> scal[2]; condest (Hager's
+// 1-norm estimate of ||R^{-1}||_1 times ||R||_1) -> scal[3].  work: 3 n doubles.
+hipError_t launch_estimators(hipStream_t s, int64_t n, const double *R, int64_t ldr,
+                             const double *RT, uint64_t seed, double *work, double *scal);
+hipError_t launch_stop_init(hipStream_t s, int32_t *state);
 hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                     const double *RT, const double *y, double *x, int32_t *status);

@@ -26,31 +26,38 @@ __device__ __forceinline__ double group_sum(double v)
 // reads G consecutive doubles.  Tiles are dealt round-robin over all waves of the grid, so at any
 // moment the grid streams one contiguous window of A; A and b are read with non-temporal loads
 // (each byte is used once, so they need not displace anything in the caches).
-template <int G, int CPL, int RT>
+// With DX, the same row loads also give t = A_row . dx and the partial of ||A dx||^2 (part_ad): for
+// dx = x_i - x_{i-1} that is ||r(x_{i-1}) - r(x_i)||^2, the left side of the stopping rule.
+// A non-null `done` flag that is set makes the launch a no-op (the stopping rule has fired).
+template <int G, int CPL, int RT, bool DX>
 __global__ void __launch_bounds__(kPassThreads)
 k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
-       const double *__restrict__ x, double *__restrict__ part, double *__restrict__ part_rr)
+       const double *__restrict__ x, double *__restrict__ part, double *__restrict__ part_rr,
+       const double *__restrict__ dx, double *__restrict__ part_ad, const int32_t *__restrict__ done)
 {
+    if (done && *done) return;
     constexpr int RPW = 64 / G;
     constexpr int TILE = RPW * RT;                   // rows per wave per tile
     constexpr int WAVES = kPassThreads / 64;
     __shared__ double s_acc[64 * CPL];
     __shared__ double s_rr[WAVES];
+    __shared__ double s_ad[WAVES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane % G, grp = lane / G;
 
-    double xr[CPL];
+    double xr[CPL], dr[CPL];
     bool cok[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int64_t col = sub + (int64_t)G * c;
         cok[c] = col < n;
         xr[c] = cok[c] ? x[col] : 0.0;
+        dr[c] = (DX && cok[c]) ? dx[col] : 0.0;
     }
     double acc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
-    double rr = 0.0;
+    double rr = 0.0, ad = 0.0;
 
     const int64_t step = (int64_t)gridDim.x * WAVES * TILE;
     for (int64_t t0 = ((int64_t)blockIdx.x * WAVES + wave) * TILE; t0 < m; t0 += step) {
@@ -74,6 +81,13 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
             dot = group_sum<G>(dot);
             const double r = bb[t] - dot;            // residual entry, FP64, before A^T
             if (sub == 0) rr = fma(r, r, rr);
+            if (DX) {
+                double td = 0.0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) td = fma(a[t][c], dr[c], td);
+                td = group_sum<G>(td);
+                if (sub == 0) ad = fma(td, td, ad);
+            }
 #pragma unroll
             for (int c = 0; c < CPL; ++c) acc[c] = fma(a[t][c], r, acc[c]);
         }
@@ -87,6 +101,11 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) rr += __shfl_xor(rr, off, 64);
     if (lane == 0) s_rr[wave] = rr;
+    if (DX) {
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) ad += __shfl_xor(ad, off, 64);
+        if (lane == 0) s_ad[wave] = ad;
+    }
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
         if (wave == w && grp == 0) {
@@ -103,6 +122,12 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) s += s_rr[w];
         part_rr[blockIdx.x] = s;
+        if (DX) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) t += s_ad[w];
+            part_ad[blockIdx.x] = t;
+        }
     }
 }
 
@@ -112,8 +137,10 @@ constexpr int kRedGroups = 16;
 
 __global__ void __launch_bounds__(64 * kRedGroups)
 k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__restrict__ part_rr,
-         double *__restrict__ c, double *__restrict__ rr_out)
+         double *__restrict__ c, double *__restrict__ rr_out, const double *__restrict__ part_ad,
+         double *__restrict__ ad_out, const int32_t *__restrict__ done)
 {
+    if (done && *done) return;
     __shared__ double s[kRedGroups][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
@@ -131,11 +158,16 @@ k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__
     if (blockIdx.x == 0 && rr_out) {
         __syncthreads();
         if (lane == 0) s[g][0] = strided_sum<8>(part_rr + p_lo, cnt, 1);
+        if (lane == 1 && part_ad) s[g][1] = strided_sum<8>(part_ad + p_lo, cnt, 1);
         __syncthreads();
         if (threadIdx.x == 0) {
-            double t = 0.0;
+            double t = 0.0, a = 0.0;
             for (int q = 0; q < kRedGroups; ++q) t += s[q][0];
             *rr_out = t;
+            if (part_ad) {
+                for (int q = 0; q < kRedGroups; ++q) a += s[q][1];
+                *ad_out = a;
+            }
         }
     }
 }
@@ -149,7 +181,7 @@ struct PassVariant {
 };
 
 template <int G, int CPL, int RT>
-const void *pass_fn() { return reinterpret_cast<const void *>(&k_pass<G, CPL, RT>); }
+const void *pass_fn() { return reinterpret_cast<const void *>(&k_pass<G, CPL, RT, true>); }
 
 PassVariant pass_variant(int64_t n)
 {
@@ -184,10 +216,15 @@ int resident_wgs(int id, const void *fn)
 
 template <int G, int CPL, int RT>
 void pass_launch(hipStream_t s, int P, int64_t m, int64_t n, const double *A, int64_t lda,
-                 const double *b, const double *x, double *part, double *part_rr)
+                 const double *b, const double *x, double *part, double *part_rr, const double *dx,
+                 double *part_ad, const int32_t *done)
 {
-    hipLaunchKernelGGL((k_pass<G, CPL, RT>), dim3(P), dim3(kPassThreads), 0, s, m, n, A, lda, b, x,
-                       part, part_rr);
+    if (dx)
+        hipLaunchKernelGGL((k_pass<G, CPL, RT, true>), dim3(P), dim3(kPassThreads), 0, s, m, n, A, lda,
+                           b, x, part, part_rr, dx, part_ad, done);
+    else
+        hipLaunchKernelGGL((k_pass<G, CPL, RT, false>), dim3(P), dim3(kPassThreads), 0, s, m, n, A, lda,
+                           b, x, part, part_rr, dx, part_ad, done);
 }
 
 }  // namespace
@@ -209,6 +246,10 @@ void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt)
     ib.P = iter_partials(m, n);
     ib.part = ar.take<double>((size_t)ib.P * (size_t)n);
     ib.part_rr = ar.take<double>((size_t)ib.P);
+    ib.part_ad = ar.take<double>((size_t)ib.P);
+    ib.dx = ar.take<double>((size_t)n);
+    ib.scal = ar.take<double>(8);
+    ib.state = ar.take<int32_t>(8);
     ib.c = ar.take<double>((size_t)n);
     ib.xprev = ar.take<double>((size_t)n);
     ib.RT = need_rt ? ar.take<double>((size_t)n * (size_t)n) : nullptr;
@@ -216,22 +257,23 @@ void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt)
 
 hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, const double *x, const IterBufs &ib, double *c,
-                           double *rnorm2, hipEvent_t ev0, hipEvent_t ev1)
+                           double *rnorm2, hipEvent_t ev0, hipEvent_t ev1, const double *dx,
+                           double *ad_out, const int32_t *done)
 {
     const int P = ib.P;
     if (ev0) {
         hipError_t e0 = hipEventRecord(ev0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (n <= 8) pass_launch<8, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 16) pass_launch<16, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 32) pass_launch<16, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 64) pass_launch<16, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 128) pass_launch<64, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 256) pass_launch<64, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 512) pass_launch<64, 8, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 1024) pass_launch<64, 16, 2>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
-    else if (n <= 2048) pass_launch<64, 32, 1>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr);
+    if (n <= 8) pass_launch<8, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 16) pass_launch<16, 1, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 32) pass_launch<16, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 64) pass_launch<16, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 128) pass_launch<64, 2, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 256) pass_launch<64, 4, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 512) pass_launch<64, 8, 4>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 1024) pass_launch<64, 16, 2>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
+    else if (n <= 2048) pass_launch<64, 32, 1>(s, P, m, n, A, lda, b, x, ib.part, ib.part_rr, dx, ib.part_ad, done);
     else return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -240,7 +282,7 @@ hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A,
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)ceil_div(n, 64)), dim3(64 * kRedGroups), 0, s, P, n, ib.part,
-                       ib.part_rr, c, rnorm2);
+                       ib.part_rr, c, rnorm2, dx ? ib.part_ad : nullptr, ad_out, done);
     return hipGetLastError();
 }
 

@@ -18,12 +18,14 @@ LS_OK, LS_ERR_ARG, LS_ERR_ALLOC, LS_ERR_DEVICE, LS_ERR_RANK, LS_ERR_NONFINITE, \
     LS_ERR_DIVERGED, LS_ERR_UNSUPPORTED = range(8)
 STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_RANK",
                 "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED"]
-OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL = \
-    1, 2, 3, 4, 5, 6, 7, 8
+OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL, \
+    OPT_STOP, OPT_GAMMA, OPT_RHO = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+NORMEST_SEED_OFFSET = 0x632BE59BD9B4E019
 
 EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_option",
            "ls_get_option", "ls_sketch_embedding", "ls_sketch_csr", "ls_sketch", "ls_qr_sketch",
-           "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile"]
+           "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile",
+           "ls_solve_info"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -65,6 +67,8 @@ def load():
         "ls_solve": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _vp], ctypes.c_int),
         "ls_sync": ([_vp, _vp], ctypes.c_int),
         "ls_profile": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64), _i32], ctypes.c_int),
+        "ls_solve_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64),
+                           ctypes.POINTER(_f64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -206,6 +210,13 @@ class Context:
 
     def sync(self):
         self._check(self._L.ls_sync(self.h, self._stream()), "ls_sync")
+
+    def solve_info(self):
+        """(d used, refinement steps made, normest, condest) of the last solve."""
+        d, q, ne, ce = _i64(), _i32(), _f64(), _f64()
+        self._check(self._L.ls_solve_info(self.h, ctypes.byref(d), ctypes.byref(q), ctypes.byref(ne),
+                                          ctypes.byref(ce)), "ls_solve_info")
+        return d.value, q.value, ne.value, ce.value
 
     def profile(self, reset: bool = True):
         """(summed fused-pass kernel ms, launches) since the last reset (needs OPT_PROFILE = 1)."""

@@ -157,3 +157,17 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(ls, "LIB_PATH", str(tmp_path / "libls.so"))
     with pytest.raises(RuntimeError, match="not built"):
         ls.load()
+
+
+def test_stop_options(L, hctx):
+    iv, dv = ctypes.c_int64(), ctypes.c_double()
+    assert L.ls_set_option(hctx, ls.OPT_STOP, 1, 0.0) == ls.LS_OK
+    assert L.ls_set_option(hctx, ls.OPT_STOP, 2, 0.0) == ls.LS_ERR_ARG
+    assert L.ls_set_option(hctx, ls.OPT_GAMMA, 0, 2.0) == ls.LS_OK
+    assert L.ls_set_option(hctx, ls.OPT_RHO, 0, -1.0) == ls.LS_ERR_ARG
+    L.ls_get_option(hctx, ls.OPT_GAMMA, ctypes.byref(iv), ctypes.byref(dv))
+    assert dv.value == 2.0
+    L.ls_get_option(hctx, ls.OPT_RHO, ctypes.byref(iv), ctypes.byref(dv))
+    assert dv.value == 0.04
+    d, q = ctypes.c_int64(), ctypes.c_int32()
+    assert L.ls_solve_info(hctx, ctypes.byref(d), ctypes.byref(q), None, None) == ls.LS_OK

@@ -435,3 +435,38 @@ def test_dimension_rule():
         w = scipy.special.lambertw(c * m / n**2 * math.log(2.0**53)).real
         assert d == max(math.ceil(a * n * math.exp(w)), 20 * n)
         assert d >= 20 * n
+
+
+# ------------------------------------------------------- Section 3.3 stopping rule (NEXT-4)
+
+@pytest.mark.parametrize("kappa,beta", [(1e1, 1e-12), (1e10, 1e-6), (1e10, 1e-3), (1e15, 1e-12), (1.0, 1e-6)])
+def test_stopping_rule_reaches_householder_accuracy(kappa, beta):
+    """Section 3.3: the rule stops at forward and residual errors a small multiple of Householder's."""
+    p = _config1(kappa=kappa, beta=beta, seed=8)
+    n, d = 50, 1000
+    g = oracle.normest_start(n, 99)
+    x, it, ne, ce = oracle.iterative_sketching_stop(p.A, p.b, n, d, 200, g, seed=p.spec.sketch_seed)
+    xh = oracle.householder_lstsq(p.Aview, p.b)[0]
+    fe, fe_h = np.linalg.norm(x - p.x_true), np.linalg.norm(xh - p.x_true)
+    assert 1 <= it < 200
+    assert fe <= 10 * max(fe_h, 1e-15) + 10 * U
+    # the estimates are within their known factors of the true values
+    _, _, R, _ = oracle.iterative_sketching(p.A, p.b, n, d, 0, seed=p.spec.sketch_seed, history=True)
+    assert 0.3 * np.linalg.norm(R, 2) <= ne <= np.linalg.norm(R, 2) * (1 + 1e-12)
+    k1 = np.linalg.norm(R, 1) * np.linalg.norm(np.linalg.inv(R), 1)
+    assert k1 / 20 <= ce <= k1 * (1 + 1e-6)
+
+
+def test_stopping_rule_stops_later_for_ill_conditioned():
+    """More conditioning -> larger error floor -> the rule stops no later than for kappa = 1 at the
+    same residual; and at kappa = 1e10, ||r|| = 1e-6 it stops well before a fixed 60 steps."""
+    p1 = _config1(kappa=1e10, beta=1e-6, seed=9)
+    g = oracle.normest_start(50, 7)
+    _, it1, _, _ = oracle.iterative_sketching_stop(p1.A, p1.b, 50, 1000, 200, g, seed=p1.spec.sketch_seed)
+    assert it1 < 60
+
+
+def test_normest_start_is_uniform():
+    g = oracle.normest_start(20000, 5)
+    assert -1.0 <= g.min() and g.max() < 1.0
+    assert abs(g.mean()) < 0.02 and abs(g.var() - 1.0 / 3.0) < 0.01
