@@ -447,10 +447,16 @@ ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R
     LS_TRY(need_device(ctx));
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double *RT = nullptr;
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { RT = ar.take<double>((size_t)n * (size_t)n); }));
+    double *RT = nullptr, *Rc = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        RT = ar.take<double>((size_t)n * (size_t)n);
+        Rc = ar.take<double>((size_t)n * (size_t)n);
+    }));
+    // R^T for the back substitution, and R again with leading dimension n (the substitution
+    // kernels address 32 rows of R from one descriptor)
     HIP_TRY(ctx, launch_transpose(s, n, R, ldr, RT), "transpose R");
-    HIP_TRY(ctx, launch_solve_update(s, n, R, ldr, RT, c, nullptr, nullptr, d, 0, 0.0, 0.0, ctx->status), "solve kernel");
+    HIP_TRY(ctx, launch_compact_upper(s, n, R, ldr, Rc), "compact R");
+    HIP_TRY(ctx, launch_solve_update(s, n, Rc, n, RT, c, nullptr, nullptr, d, 0, 0.0, 0.0, ctx->status), "solve kernel");
     return LS_OK;
 }
 
@@ -474,17 +480,22 @@ ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doub
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     IterBufs ib{};
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { iter_bufs(ar, m, n, ib, true); }));
+    double *Rc = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        iter_bufs(ar, m, n, ib, true);
+        Rc = ar.take<double>((size_t)n * (size_t)n);
+    }));
     int mode;
     double alpha, beta;
     update_params(ctx, n, 0, mode, alpha, beta);
     if (ctx->update == 2 && ctx->beta < 0.0) return ls_fail(ctx, LS_ERR_ARG, "momentum in ls_iterate needs LS_OPT_BETA");
     HIP_TRY(ctx, launch_transpose(s, n, R, ldr, ib.RT), "transpose R");
+    HIP_TRY(ctx, launch_compact_upper(s, n, R, ldr, Rc), "compact R");
     if (mode == 2)
         HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
     for (int32_t i = 0; i < q; ++i) {
         LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, rnorm2 ? rnorm2 + i : nullptr));
-        HIP_TRY(ctx, launch_solve_update(s, n, R, ldr, ib.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status), "solve kernel");
+        HIP_TRY(ctx, launch_solve_update(s, n, (const double *)Rc, n, ib.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status), "solve kernel");
     }
     return LS_OK;
 }

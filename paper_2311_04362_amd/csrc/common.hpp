@@ -56,13 +56,13 @@ struct Arena {
 };
 
 // Sum of count values p[0], p[stride], ... added in ascending order, U loads in flight at a time.
-template <int U>
-__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int count, int64_t stride)
+template <int U, typename T>
+__device__ __forceinline__ T strided_sum(const T *__restrict__ p, int count, int64_t stride)
 {
-    double acc = 0.0;
+    T acc = T(0);
     int g = 0;
     for (; g + U <= count; g += U) {
-        double v[U];
+        T v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(g + u) * stride];
 #pragma unroll
@@ -73,14 +73,13 @@ __device__ __forceinline__ double strided_sum(const double *__restrict__ p, int 
 }
 
 // sum_i p[i * stride] * w[i] for i < count, accumulated in ascending i, U loads in flight.
-template <int U>
-__device__ __forceinline__ double strided_dot(const double *__restrict__ p, int64_t stride,
-                                              const double *w, int count)
+template <int U, typename T>
+__device__ __forceinline__ T strided_dot(const T *__restrict__ p, int64_t stride, const T *w, int count)
 {
-    double acc = 0.0;
+    T acc = T(0);
     int i = 0;
     for (; i + U <= count; i += U) {
-        double v[U];
+        T v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(i + u) * stride];
 #pragma unroll
@@ -150,6 +149,9 @@ struct IterBufs {
 int32_t iter_partials(int64_t m, int64_t n);
 void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt);
 hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT);
+hipError_t launch_transpose(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *RT);
+// Upper triangle of R copied with leading dimension n, zero below the diagonal.
+hipError_t launch_compact_upper(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *Rc);
 hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, const double *x, const IterBufs &ib, double *c,
                            double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
@@ -157,21 +159,34 @@ hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A,
                            const int32_t *done = nullptr);
 // Stopping rule of Section 3.3 evaluated on the device (see k_solve).
 struct StopArgs {
-    int32_t *state = nullptr;   // [0] done flag, [1] updates made (nullptr: no stopping rule)
-    double *scal = nullptr;     // [0] ||r_i||^2, [1] ||A dx||^2, [2] normest, [3] condest, [4] ||r_0||^2
+    int32_t *state = nullptr;   // [0] done flag, [1] updates made, [2] fall back to FP64, [3] growth run
+                                // (nullptr: no done flag, no stopping rule, no growth monitor)
+    double *scal = nullptr;     // [0] ||r_i||^2, [1] ||A dx||^2, [2] normest, [3] condest,
+                                // [4] ||r_0||^2, [5] previous ||r||^2
     double *dx = nullptr;       // n: x_i - x_{i-1}, written by each update
     double gamma = 1.0, rho = 0.04;
     int check = 0;              // 1 when scal[1] holds ||A (x_i - x_{i-1})||^2 for this step
+    int grow = 0;               // 1: monitor the growth of ||r_i|| (mixed precision)
 };
-// d = R^{-1} R^{-T} c; mode 0: write d to dout; mode 1: x += d; mode 2: x += alpha d + beta (x - xprev)
+// d = R^{-1} R^{-T} c; mode 0: write d to dout; mode 1: x += d; mode 2: x += alpha d + beta (x - xprev).
+// With an FP32 factor the solves run in FP32 on c scaled by a power of two; c, x and d stay FP64.
 hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                const double *RT, const double *c, double *x, double *xprev,
                                double *dout, int mode, double alpha, double beta, int32_t *status,
                                const StopArgs &st = StopArgs());
+hipError_t launch_solve_update(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                               const float *RT, const double *c, double *x, double *xprev,
+                               double *dout, int mode, double alpha, double beta, int32_t *status,
+                               const StopArgs &st = StopArgs());
 // normest (power method from a SplitMix64 start, ceil(ln n) steps) -> scal[2]; condest (Hager's
-// 1-norm estimate of ||R^{-1}||_1 times ||R||_1) -> scal[3].  work: 3 n doubles.
+// 1-norm estimate of ||R^{-1}||_1 times ||R||_1) -> scal[3], in the factor's arithmetic.
+// work: 3 n entries.
 hipError_t launch_estimators(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                              const double *RT, uint64_t seed, double *work, double *scal);
+hipError_t launch_estimators(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                             const float *RT, uint64_t seed, float *work, double *scal);
 hipError_t launch_stop_init(hipStream_t s, int32_t *state);
 hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                     const double *RT, const double *y, double *x, int32_t *status);
+hipError_t launch_back_substitution(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                                    const float *RT, const float *y, double *x, int32_t *status);

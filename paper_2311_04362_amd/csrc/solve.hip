@@ -7,11 +7,15 @@
 //                 as coalesced GEMV updates; no inverse matrix is ever formed), then the update.
 //   k_back        back substitution alone (x_0).
 //   k_transpose   R^T for the column reads of the back substitution.
+//
+// Every kernel is instantiated for FP64 and for FP32 factors.  With an FP32 factor (mixed precision)
+// the right-hand side is scaled by a power of two that brings its largest entry into [1/2, 1),
+// rounded once to FP32, solved in FP32, and scaled back exactly in FP64; the update stays FP64.
 #include "common.hpp"
 
 namespace {
 
-__device__ __forceinline__ double readlane_f64(double v, int l)
+__device__ __forceinline__ double readlane(double v, int l)
 {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
     const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xFFFFFFFFull), l);
@@ -19,178 +23,413 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+__device__ __forceinline__ float readlane(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Buffer-descriptor loads for the GEMV updates: the lane's byte offset travels in a VGPR and the
+// row's byte offset, uniform across the wave, in an SGPR, so 32 loads in flight cost no address
+// registers.  The descriptor covers `bytes` bytes from `base` (at most 2^31 - 1).  The hardware
+// range check is not relied on: callers load only rows that exist and clamp the column index of
+// lanes that have nothing to load into the matrix.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *base, int64_t bytes)
+{
+    const int nb = (int)(bytes <= 0 ? 0 : (bytes < 0x7FFFFFFF ? bytes : 0x7FFFFFFF));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base), (short)0, nb, 0x00020000);
+}
+
+__device__ __forceinline__ double rows_load(__amdgpu_buffer_rsrc_t rs, double *, uint32_t vbytes, uint32_t sbytes)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vbytes, (int)sbytes, 0));
+}
+
+__device__ __forceinline__ float rows_load(__amdgpu_buffer_rsrc_t rs, float *, uint32_t vbytes, uint32_t sbytes)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vbytes, (int)sbytes, 0));
+}
+
+// sum over u < kSB of M[u][j] w[u] in ascending u (M row-major with leading dimension ld, behind
+// the descriptor rs), all loads issued first.  Rows from `count` on repeat row count-1 and must meet
+// zeros in w.
+template <typename T, int kSB>
+__device__ __forceinline__ T rows_dot(__amdgpu_buffer_rsrc_t rs, int64_t ld, int64_t j, const T *w, int count)
+{
+    T v[kSB];
+#pragma unroll
+    for (int u = 0; u < kSB; ++u)
+        v[u] = rows_load(rs, (T *)nullptr, (uint32_t)(j * (int64_t)sizeof(T)),
+                         (uint32_t)((u < count ? u : count - 1) * ld * (int64_t)sizeof(T)));
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < kSB; ++u) acc += v[u] * w[u];
+    return acc;
+}
+
 // Diagonal block of the substitutions used by the library, and the solve kernels' work-group size.
 constexpr int kSolveBlock = 32;
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 512;
 
 // LDS of the substitution kernels: double-buffered diagonal block, the reciprocals of its diagonal,
 // and the block of R that couples the current block of unknowns to the next one.
-template <int kSB>
+template <typename T, int kSB>
 struct SubstLds {
-    double diag[2][kSB][kSB + 1];
-    double rdiag[2][kSB];
-    double off[2][kSB][kSB + 1];
+    T diag[2][kSB][kSB + 1];
+    T rdiag[2][kSB];
+    T off[2][kSB][kSB + 1];
 };
 
-// dst = R[r0:r0+kSB, c0:c0+kSB] (zero outside the n x n matrix), read by threads t.. of the WG.
-template <int kSB>
-__device__ __forceinline__ void load_block(double (*dst)[kSB + 1], const double *__restrict__ R,
-                                           int64_t ldr, int64_t n, int64_t r0, int64_t c0, int t,
-                                           int nt)
-{
-    for (int e = t; e < kSB * kSB; e += nt) {
-        const int r = e / kSB, c = e % kSB;
-        const int64_t gr = r0 + r, gc = c0 + c;
-        dst[r][c] = (gr >= 0 && gr < n && gc >= 0 && gc < n) ? R[gr * ldr + gc] : 0.0;
-    }
-}
+// The LDS data of diagonal block b, numbered e < 2 kSB^2 + kSB: the diagonal block, the coupling
+// block (forward: R[b, b+1], the terms of block b in the equations of block b+1; backward:
+// R[b-1, b]) and the reciprocals of the diagonal.  Zero (reciprocal one) outside the n x n matrix.
+// The load always reads a valid address (clamped into the matrix) and the value is fixed up when it
+// is stored, so a wave issues all its loads without waiting on any of them.
+template <typename T, int kSB>
+struct BlockData {
+    static constexpr int kCount = 2 * kSB * kSB + kSB;
 
-// Reciprocals of R[i0+l, i0+l] (1 outside R), by threads t.. of the WG.
-template <int kSB>
-__device__ __forceinline__ void load_rdiag(double *dst, const double *__restrict__ R, int64_t ldr,
-                                           int64_t n, int64_t i0, int t, int nt)
-{
-    for (int l = t; l < kSB; l += nt) {
-        const int64_t g = i0 + l;
-        dst[l] = (g >= 0 && g < n) ? 1.0 / R[g * ldr + g] : 1.0;
+    template <bool kForward>
+    static __device__ __forceinline__ void where(int64_t n, int b, int e, int64_t &r, int64_t &c, bool &inside)
+    {
+        const int64_t b0 = (int64_t)b * kSB;
+        if (e < kSB * kSB) {
+            r = b0 + e / kSB;
+            c = b0 + e % kSB;
+        } else if (e < 2 * kSB * kSB) {
+            const int f = e - kSB * kSB;
+            r = (kForward ? b0 : b0 - kSB) + f / kSB;
+            c = (kForward ? b0 + kSB : b0) + f % kSB;
+        } else {
+            r = c = b0 + (e - 2 * kSB * kSB);
+        }
+        inside = r >= 0 && r < n && c >= 0 && c < n;
     }
-}
+
+    template <bool kForward>
+    static __device__ __forceinline__ T load(const T *__restrict__ R, int64_t ldr, int64_t n, int b, int e)
+    {
+        int64_t r, c;
+        bool inside;
+        where<kForward>(n, b, e, r, c, inside);
+        r = r < 0 ? 0 : (r < n ? r : n - 1);
+        c = c < 0 ? 0 : (c < n ? c : n - 1);
+        return R[r * ldr + c];
+    }
+
+    template <bool kForward>
+    static __device__ __forceinline__ void store(SubstLds<T, kSB> &L, int buf, int64_t n, int b, int e, T raw)
+    {
+        int64_t r, c;
+        bool inside;
+        where<kForward>(n, b, e, r, c, inside);
+        if (e < kSB * kSB) L.diag[buf][e / kSB][e % kSB] = inside ? raw : T(0);
+        else if (e < 2 * kSB * kSB) L.off[buf][(e - kSB * kSB) / kSB][(e - kSB * kSB) % kSB] = inside ? raw : T(0);
+        else L.rdiag[buf][e - 2 * kSB * kSB] = inside ? T(1) / raw : T(1);
+    }
+};
+
+// One block's LDS data staged in the registers of wave 1 (the stager): loaded a step before it is
+// needed, written to the idle LDS buffer the step after.  Element e = lane + 64 p of BlockData's
+// numbering sits in v[p]: p < 16 the diagonal block (row 2p + lane/32, column lane%32), p < 32 the
+// coupling block (same pattern), p = 32 the diagonal entries (lanes < 32).  Away from the edges of
+// the matrix the loads go through two buffer descriptors with the row offsets in SGPRs, so a step
+// costs 33 loads and 33 LDS writes; blocks that touch an edge take the clamped element-wise path.
+template <typename T, int kSB>
+struct Stage {
+    static_assert(kSB == 32, "two rows of a 32-wide block per 64-lane access");
+    static constexpr int kPer = 33;
+    T v[kPer];
+
+    template <bool kForward>
+    static __device__ __forceinline__ bool edge(int64_t n, int b)
+    {
+        const int64_t b0 = (int64_t)b * kSB;
+        return kForward ? (b0 + 2 * kSB > n) : (b < 1 || b0 + kSB > n);
+    }
+
+    template <bool kForward>
+    __device__ __forceinline__ void load(const T *__restrict__ R, int64_t ldr, int64_t n, int b, int lane)
+    {
+        const int64_t b0 = (int64_t)b * kSB;
+        if (edge<kForward>(n, b)) {
+#pragma unroll
+            for (int p = 0; p < kPer; ++p) {
+                const int e = lane + p * 64;
+                v[p] = BlockData<T, kSB>::template load<kForward>(R, ldr, n, b, e < BlockData<T, kSB>::kCount ? e : 0);
+            }
+            return;
+        }
+        const int64_t span = ((int64_t)(kSB - 1) * ldr + kSB) * (int64_t)sizeof(T);
+        const auto rd = rows_rsrc(R + b0 * ldr + b0, span);
+        const auto ro = rows_rsrc(kForward ? R + b0 * ldr + b0 + kSB : R + (b0 - kSB) * ldr + b0, span);
+        const uint32_t vo = (uint32_t)(((int64_t)(lane >> 5) * ldr + (lane & 31)) * (int64_t)sizeof(T));
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            const uint32_t so = (uint32_t)(2 * p * ldr * (int64_t)sizeof(T));
+            v[p] = rows_load(rd, (T *)nullptr, vo, so);
+            v[16 + p] = rows_load(ro, (T *)nullptr, vo, so);
+        }
+        v[32] = rows_load(rd, (T *)nullptr, (uint32_t)((int64_t)(lane & 31) * (ldr + 1) * (int64_t)sizeof(T)), 0u);
+    }
+
+    template <bool kForward>
+    __device__ __forceinline__ void store(SubstLds<T, kSB> &L, int buf, int64_t n, int b, int lane) const
+    {
+        if (edge<kForward>(n, b)) {
+#pragma unroll
+            for (int p = 0; p < kPer; ++p) {
+                const int e = lane + p * 64;
+                if (e < BlockData<T, kSB>::kCount) BlockData<T, kSB>::template store<kForward>(L, buf, n, b, e, v[p]);
+            }
+            return;
+        }
+        const int r = lane >> 5, c = lane & 31;
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            L.diag[buf][2 * p + r][c] = v[p];
+            L.off[buf][2 * p + r][c] = v[16 + p];
+        }
+        if (lane < 32) L.rdiag[buf][lane] = T(1) / v[32];
+    }
+};
+
+// Rows of R (forward) or R^T (backward) that each GEMV wave prefetches for the next step's update:
+// 32 entries of one unknown per slot, 128 VGPRs either way (the 512-thread work-group leaves 256
+// VGPRs per wave; the estimators, which keep more state, use one slot).
+template <typename T>
+struct Prefetch {
+    static constexpr int kSlots = sizeof(T) == 8 ? 2 : 4;
+};
 
 // Solves one diagonal block in wave 0: lane l holds unknown l (v) and column l of the block
-// (colv[li] = T[li][l] of the triangular factor being applied, T = R^T forward or R backward);
-// unknown li = v_li * (1 / T[li][li]) is broadcast with readlane and removed from the others.
-template <int kSB, bool kForward>
-__device__ __forceinline__ double block_solve(double v, const double (*diag)[kSB + 1],
-                                              const double *rdiag, int nb, int lane)
+// (col[li] = T[li][l] of the triangular factor being applied, T = R^T forward or R backward).
+// Each lane scales its equation by the rounded reciprocal of its diagonal entry first, so unknown
+// li is lane li's value itself: it is broadcast with readlane and removed from every lane.  (This
+// is substitution on the system with unit diagonal; every entry carries one extra rounding.)  The
+// factor's other triangle is zero (the library only hands the kernels R with a zero lower
+// triangle), so lanes already solved or not yet reached keep their value, and lane li's own entry
+// goes to the result.  A partial last block is padded (zero entries, unit reciprocals, zero
+// unknowns), so the loop has no branch; the column is read from LDS before the loop.  Lanes
+// 32..63 compute values nobody reads.
+template <typename T, int kSB, bool kForward>
+__device__ __forceinline__ T block_solve(T v, const T (*diag)[kSB + 1], const T *rdiag, int lane)
 {
-    const int lc = (lane < kSB) ? lane : 0;
-    const double rd = rdiag[lc];
-#define colv(li) (kForward ? diag[li][lc] : diag[lc][li])
-    if (kForward) {
+    const int lc = lane & (kSB - 1);
+    const T rd = rdiag[lc];
+    T col[kSB];
 #pragma unroll
-        for (int li = 0; li < kSB; ++li) {
-            if (li < nb) {
-                const double yi = readlane_f64(v * rd, li);
-                if (lane == li) v = yi;
-                else if (lane > li && lane < nb) v -= colv(li) * yi;
-            }
-        }
-    } else {
+    for (int li = 0; li < kSB; ++li) col[li] = (kForward ? diag[li][lc] : diag[lc][li]) * rd;
+    v *= rd;
+    T res = T(0);
 #pragma unroll
-        for (int li = kSB - 1; li >= 0; --li) {
-            if (li < nb) {
-                const double zi = readlane_f64(v * rd, li);
-                if (lane == li) v = zi;
-                else if (lane < li) v -= colv(li) * zi;
-            }
-        }
+    for (int q = 0; q < kSB; ++q) {
+        const int li = kForward ? q : kSB - 1 - q;
+        const T yi = readlane(v, li);
+        v -= col[li] * yi;
+        res = (lane == li) ? yi : res;
     }
-#undef colv
-    return v;
+    return res;
 }
 
-// Forward substitution R^T y = v in place on s[0:n] (R upper triangular, row-major).
-// Block k of unknowns is solved by wave 0 alone (block_solve); wave 0 then forms the contribution
-// of block k to block k+1 in registers (the "carry").  Meanwhile waves 1.. apply block k-1 to every
-// unknown past block k+1 (coalesced reads of rows of R, 32 loads in flight per thread) and load the
-// next diagonal, reciprocal and coupling blocks into the other LDS buffer.  Each unknown therefore
-// receives the terms of earlier blocks in a fixed order, and no two waves write one entry in one
-// phase.  Unknowns are divided by R_ii as multiplication by the rounded reciprocal.
-template <int kSB>
-__device__ __forceinline__ void fwd_subst(int64_t n, const double *__restrict__ R, int64_t ldr, double *s,
-                                          SubstLds<kSB> &L)
+// Contribution of the solved block (y, one unknown per lane) to the next block's unknowns:
+// lane l gets sum over li of cpl(li, l) y_li, in four interleaved partial sums added pairwise.
+template <typename T, int kSB, bool kForward>
+__device__ __forceinline__ T block_carry(T y, const T (*off)[kSB + 1], int lane)
 {
+    const int lc = lane & (kSB - 1);
+    T o[kSB];
+#pragma unroll
+    for (int li = 0; li < kSB; ++li) o[li] = kForward ? off[li][lc] : off[lc][li];
+    T a[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int li = 0; li < kSB; ++li) a[li & 3] += o[li] * readlane(y, li);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// Forward substitution R^T y = v in place on s[] (R upper triangular with a zero lower triangle,
+// row-major; s holds n unknowns followed by zeros up to a multiple of kSB), by a work-group of
+// kThreads threads in three roles.  Each role runs its own loop with one barrier per block (the
+// barrier counts waves, so the loops stay in step), which keeps their registers and their
+// outstanding loads apart.
+//   wave 0 (solver), step k:  solves block k (block_solve) and forms its contribution to block k+1
+//                             (the "carry", block_carry).
+//   wave 1 (stager), step k:  writes the LDS data of block k+1, loaded during step k-1, into the
+//                             idle buffer, then loads block k+2's.
+//   waves 2.. (GEMV), step k: apply block k-1 to every unknown past block k+1, over rows of R loaded
+//                             during step k-1 (unknowns beyond the prefetch slots load theirs in the
+//                             step), then load the rows of block k for step k+1.
+// So no load of R waits on the solver's critical path.  Each unknown receives the terms of earlier
+// blocks in a fixed order, and no two waves write one entry in one phase.  Unknowns are divided by
+// R_ii as multiplication by the rounded reciprocal.
+template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots>
+__device__ __forceinline__ void fwd_subst(int64_t n, const T *__restrict__ R, int64_t ldr, T *s,
+                                          SubstLds<T, kSB> &L)
+{
+    constexpr int kG = kThreads - 128;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (int)((n + kSB - 1) / kSB);
-    load_block<kSB>(L.diag[0], R, ldr, n, 0, 0, tid, blockDim.x);
-    load_rdiag<kSB>(L.rdiag[0], R, ldr, n, 0, tid, blockDim.x);
-    load_block<kSB>(L.off[0], R, ldr, n, 0, kSB, tid, blockDim.x);
+    for (int e = tid; e < BlockData<T, kSB>::kCount; e += kThreads)
+        BlockData<T, kSB>::template store<true>(L, 0, n, 0, e, BlockData<T, kSB>::template load<true>(R, ldr, n, 0, e));
+    if (wave == 0) {
+        __syncthreads();
+        T carry = T(0);
+        for (int k = 0; k < nblk; ++k) {
+            const int64_t i0 = (int64_t)k * kSB;
+            const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
+            const int buf = k & 1;
+            T v = (lane < nb) ? s[i0 + lane] - carry : T(0);
+            v = block_solve<T, kSB, true>(v, L.diag[buf], L.rdiag[buf], lane);
+            if (lane < nb) s[i0 + lane] = v;
+            if (k + 1 < nblk) carry = block_carry<T, kSB, true>(v, L.off[buf], lane);
+            __syncthreads();
+        }
+        return;
+    }
+    if (wave == 1) {
+        Stage<T, kSB> stage;
+        if (nblk > 1) stage.template load<true>(R, ldr, n, 1, lane);
+        __syncthreads();
+        for (int k = 0; k < nblk; ++k) {
+            if (k + 1 < nblk) stage.template store<true>(L, (k & 1) ^ 1, n, k + 1, lane);
+            if (k + 2 < nblk) stage.template load<true>(R, ldr, n, k + 2, lane);
+            __syncthreads();
+        }
+        return;
+    }
+    const int th = tid - 128;
+    T pr[kPF][kSB];
     __syncthreads();
-    double carry = 0.0;
     for (int k = 0; k < nblk; ++k) {
         const int64_t i0 = (int64_t)k * kSB;
-        const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
-        const int buf = k & 1;
-        double next = 0.0;
-        if (wave == 0) {
-            double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
-            v = block_solve<kSB, true>(v, L.diag[buf], L.rdiag[buf], nb, lane);
-            if (lane < nb) s[i0 + lane] = v;
-            if (k + 1 < nblk) {
-                const int lc = (lane < kSB) ? lane : 0;
+        const int64_t lo = i0 + kSB;                    // first unknown past block k
+        if (k >= 1) {                                   // block k-1 (always full) -> unknowns lo..n-1
+            const int64_t p0 = i0 - kSB;
 #pragma unroll
-                for (int li = 0; li < kSB; ++li)
-                    if (li < nb) next += L.off[buf][li][lc] * readlane_f64(v, li);
+            for (int r = 0; r < kPF; ++r) {
+                const int64_t j = lo + th + (int64_t)r * kG;
+                if (j < n) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int u = 0; u < kSB; ++u) acc += pr[r][u] * s[p0 + u];
+                    s[j] -= acc;
+                }
             }
-        } else {
-            const int t = tid - 64, nt = blockDim.x - 64;
-            if (k >= 1) {                               // block k-1 (always full) -> past block k+1
-                const int64_t p0 = i0 - kSB;
-                for (int64_t j = i0 + kSB + t; j < n; j += nt)
-                    s[j] -= strided_dot<kSB>(R + p0 * ldr + j, ldr, s + p0, kSB);
+            if (lo + (int64_t)kPF * kG + th < n) {
+                const auto rs = rows_rsrc(R + p0 * ldr, ((int64_t)(kSB - 1) * ldr + n) * (int64_t)sizeof(T));
+                for (int64_t j = lo + (int64_t)kPF * kG + th; j < n; j += kG)
+                    s[j] -= rows_dot<T, kSB>(rs, ldr, j, s + p0, kSB);
             }
-            if (k + 1 < nblk) {
-                load_block<kSB>(L.diag[buf ^ 1], R, ldr, n, i0 + kSB, i0 + kSB, t, nt);
-                load_rdiag<kSB>(L.rdiag[buf ^ 1], R, ldr, n, i0 + kSB, t, nt);
-                load_block<kSB>(L.off[buf ^ 1], R, ldr, n, i0 + kSB, i0 + 2 * kSB, t, nt);
+        }
+        if (k + 1 < nblk) {                             // rows of block k (full) for unknowns lo+kSB..
+            const auto rs = rows_rsrc(R + i0 * ldr, ((int64_t)(kSB - 1) * ldr + n) * (int64_t)sizeof(T));
+#pragma unroll
+            for (int r = 0; r < kPF; ++r) {
+                const int64_t q0 = (int64_t)(wave - 2) * 64 + (int64_t)r * kG;   // first slot of the wave
+                if (lo + kSB + q0 < n) {                // wave-uniform
+                    const int64_t j = lo + kSB + th + (int64_t)r * kG;
+                    const int64_t jc = j < n ? j : n - 1;
+#pragma unroll
+                    for (int u = 0; u < kSB; ++u)
+                        pr[r][u] = rows_load(rs, (T *)nullptr, (uint32_t)(jc * (int64_t)sizeof(T)),
+                                             (uint32_t)(u * ldr * (int64_t)sizeof(T)));
+                }
             }
         }
         __syncthreads();
-        carry = next;
     }
 }
 
-// Back substitution R z = v in place on s[0:n]; RT = R^T (row-major, ld n) gives the columns of R
-// contiguously for the far updates.  Same schedule as fwd_subst, blocks taken from the last.
-template <int kSB>
-__device__ __forceinline__ void back_subst(int64_t n, const double *__restrict__ R, int64_t ldr,
-                                           const double *__restrict__ RT, double *s, SubstLds<kSB> &L)
+// Back substitution R z = v in place on s[] (padded as in fwd_subst); RT = R^T (row-major, ld n)
+// gives the columns of R contiguously for the GEMV updates.  Same roles as fwd_subst, blocks taken
+// from the last; the GEMV waves apply block B+1 to unknowns 0..B*kSB-1.
+template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots>
+__device__ __forceinline__ void back_subst(int64_t n, const T *__restrict__ R, int64_t ldr,
+                                           const T *__restrict__ RT, T *s, SubstLds<T, kSB> &L)
 {
+    constexpr int kG = kThreads - 128;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (int)((n + kSB - 1) / kSB);
-    const int64_t last0 = (int64_t)(nblk - 1) * kSB;
-    load_block<kSB>(L.diag[0], R, ldr, n, last0, last0, tid, blockDim.x);
-    load_rdiag<kSB>(L.rdiag[0], R, ldr, n, last0, tid, blockDim.x);
-    load_block<kSB>(L.off[0], R, ldr, n, last0 - kSB, last0, tid, blockDim.x);  // rows of block B-1
+    for (int e = tid; e < BlockData<T, kSB>::kCount; e += kThreads)
+        BlockData<T, kSB>::template store<false>(L, 0, n, nblk - 1, e,
+                                                 BlockData<T, kSB>::template load<false>(R, ldr, n, nblk - 1, e));
+    if (wave == 0) {
+        __syncthreads();
+        T carry = T(0);
+        for (int t = 0; t < nblk; ++t) {
+            const int B = nblk - 1 - t;
+            const int64_t i0 = (int64_t)B * kSB;
+            const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
+            const int buf = t & 1;
+            T v = (lane < nb) ? s[i0 + lane] - carry : T(0);
+            v = block_solve<T, kSB, false>(v, L.diag[buf], L.rdiag[buf], lane);
+            if (lane < nb) s[i0 + lane] = v;
+            if (B >= 1) carry = block_carry<T, kSB, false>(v, L.off[buf], lane);
+            __syncthreads();
+        }
+        return;
+    }
+    if (wave == 1) {
+        Stage<T, kSB> stage;
+        if (nblk > 1) stage.template load<false>(R, ldr, n, nblk - 2, lane);
+        __syncthreads();
+        for (int t = 0; t < nblk; ++t) {
+            const int B = nblk - 1 - t;
+            if (B >= 1) stage.template store<false>(L, (t & 1) ^ 1, n, B - 1, lane);
+            if (B >= 2) stage.template load<false>(R, ldr, n, B - 2, lane);
+            __syncthreads();
+        }
+        return;
+    }
+    const int th = tid - 128;
+    T pr[kPF][kSB];
     __syncthreads();
-    double carry = 0.0;
     for (int t = 0; t < nblk; ++t) {
         const int B = nblk - 1 - t;
         const int64_t i0 = (int64_t)B * kSB;
-        const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
-        const int buf = t & 1;
-        double next = 0.0;
-        if (wave == 0) {
-            double v = (lane < nb) ? s[i0 + lane] - carry : 0.0;
-            v = block_solve<kSB, false>(v, L.diag[buf], L.rdiag[buf], nb, lane);
-            if (lane < nb) s[i0 + lane] = v;
-            if (B >= 1) {
-                const int lc = (lane < kSB) ? lane : 0;
+        if (t >= 1) {                                   // block B+1 -> unknowns 0..i0-1
+            const int64_t p0 = i0 + kSB;
 #pragma unroll
-                for (int li = 0; li < kSB; ++li)
-                    if (li < nb) next += L.off[buf][lc][li] * readlane_f64(v, li);
+            for (int r = 0; r < kPF; ++r) {
+                const int64_t j = th + (int64_t)r * kG;
+                if (j < i0) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int u = 0; u < kSB; ++u) acc += pr[r][u] * s[p0 + u];   // padded s: zero past n
+                    s[j] -= acc;
+                }
             }
-        } else {
-            const int th = tid - 64, nt = blockDim.x - 64;
-            if (t >= 1) {                               // block B+1 -> blocks B-1, B-2, ...
-                const int64_t p0 = i0 + kSB;
+            if ((int64_t)kPF * kG + th < i0) {
                 const int pb = (int)((p0 + kSB < n) ? kSB : n - p0);
-                for (int64_t j = th; j < i0; j += nt)
-                    s[j] -= strided_dot<kSB>(RT + p0 * n + j, n, s + p0, pb);
+                const auto rs = rows_rsrc(RT + p0 * n, (n - p0) * n * (int64_t)sizeof(T));
+                for (int64_t j = (int64_t)kPF * kG + th; j < i0; j += kG)
+                    s[j] -= rows_dot<T, kSB>(rs, n, j, s + p0, pb);
             }
-            if (B >= 1) {
-                load_block<kSB>(L.diag[buf ^ 1], R, ldr, n, i0 - kSB, i0 - kSB, th, nt);
-                load_rdiag<kSB>(L.rdiag[buf ^ 1], R, ldr, n, i0 - kSB, th, nt);
-                load_block<kSB>(L.off[buf ^ 1], R, ldr, n, i0 - 2 * kSB, i0 - kSB, th, nt);
+        }
+        if (B >= 1) {                                   // columns of block B for unknowns 0..i0-kSB-1
+            const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
+            const auto rs = rows_rsrc(RT + i0 * n, (n - i0) * n * (int64_t)sizeof(T));
+#pragma unroll
+            for (int r = 0; r < kPF; ++r) {
+                const int64_t q0 = (int64_t)(wave - 2) * 64 + (int64_t)r * kG;
+                if (q0 < i0 - kSB) {                    // wave-uniform
+                    const int64_t j = th + (int64_t)r * kG;
+                    const int64_t jc = j < n ? j : n - 1;
+                    // rows past n (partial last block) repeat row n-1: they meet zeros in s
+#pragma unroll
+                    for (int u = 0; u < kSB; ++u)
+                        pr[r][u] = rows_load(rs, (T *)nullptr, (uint32_t)(jc * (int64_t)sizeof(T)),
+                                             (uint32_t)((u < nb ? u : nb - 1) * n * (int64_t)sizeof(T)));
+                }
             }
         }
         __syncthreads();
-        carry = next;
     }
 }
 
 // Block-wide sum in a fixed order (wave reductions, then the waves in order); all threads get it.
-__device__ __forceinline__ double block_sum(double v, double *red)
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *red)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -198,9 +437,51 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    double t = 0.0;
+    T t = T(0);
     for (int w = 0; w < nw; ++w) t += red[w];
     return t;
+}
+
+// Block-wide maximum; all threads get it.
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+    return t;
+}
+
+// Unknowns of the substitutions live in LDS padded to a multiple of the block (zeros past n).
+template <int kSB>
+__host__ __device__ constexpr int64_t padded(int64_t n) { return (n + kSB - 1) / kSB * kSB; }
+
+template <typename T, int kSB>
+__device__ __forceinline__ void zero_pad(int64_t n, T *s)
+{
+    for (int64_t j = n + threadIdx.x; j < padded<kSB>(n); j += blockDim.x) s[j] = T(0);
+}
+
+// Right-hand side c (FP64) into the solve type: unchanged for FP64; for FP32, scaled by 2^-e with
+// e the exponent of max |c| (frexp: max |c| 2^-e in [1/2, 1)) and rounded once.  Returns e.
+template <typename T>
+__device__ __forceinline__ int load_rhs(int64_t n, const double *__restrict__ c, T *s, double *red)
+{
+    if (sizeof(T) == 8) {
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = (T)c[j];
+        return 0;
+    }
+    double mx = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) mx = fmax(mx, fabs(c[j]));
+    mx = block_max(mx, red);
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = (T)ldexp(c[j], -e);
+    return e;
 }
 
 // d = R^{-1} (R^{-T} c), then the update selected by mode (see launch_solve_update).  With a
@@ -209,52 +490,67 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 //   ||r(x_i) - r(x_{i-1})|| <= u (gamma normest ||x_i|| + rho condest ||r(x_i)||),  u = 2^-53,
 // is evaluated first (||r(x_i)||^2 and ||A (x_i - x_{i-1})||^2 come from this step's pass) and, if it
 // holds, x_i is kept and the done flag raised.  A residual that grew beyond 100 ||r(x_0)|| also
-// stops the iteration and flags ST_DIVERGED.
-template <int kSB>
+// stops the iteration and flags ST_DIVERGED.  With st.grow set (mixed precision), a residual that
+// grew three steps in a row, each time by more than a relative 2^-20, raises the done flag and
+// state[2] = 1: the caller then falls back to FP64.
+template <typename T, int kSB>
 __global__ void __launch_bounds__(kSolveThreads)
-k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
+k_solve(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT,
         const double *__restrict__ c, double *__restrict__ x, double *__restrict__ xprev,
         double *__restrict__ dout, int mode, double alpha, double beta, int32_t *__restrict__ status,
         int32_t *__restrict__ st_state, double *__restrict__ st_scal, double *__restrict__ st_dx,
-        double st_gamma, double st_rho, int st_check)
+        double st_gamma, double st_rho, int st_check, int st_grow)
 {
-    struct {
-        int32_t *state;
-        double *scal, *dx;
-        double gamma, rho;
-        int check;
-    } st = {st_state, st_scal, st_dx, st_gamma, st_rho, st_check};
-    extern __shared__ double s[];
-    __shared__ SubstLds<kSB> L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *s = reinterpret_cast<T *>(smem);
+    __shared__ SubstLds<T, kSB> L;
     __shared__ double red[kSolveThreads / 64];
-    if (st.state) {
-        if (st.state[0]) return;
-        if (st.check) {
+    if (st_state) {
+        if (st_state[0]) return;
+        if (st_check) {
             double xx = 0.0;
             for (int64_t j = threadIdx.x; j < n; j += blockDim.x) xx += x[j] * x[j];
             xx = block_sum(xx, red);
-            const double rr = st.scal[0], ad = st.scal[1];
+            const double rr = st_scal[0], ad = st_scal[1];
             const double u = 0x1p-53;
-            const bool stop = sqrt(ad) <= u * (st.gamma * st.scal[2] * sqrt(xx) + st.rho * st.scal[3] * sqrt(rr));
-            const bool diverged = !(rr <= 1e4 * st.scal[4]);
+            const bool stop = sqrt(ad) <= u * (st_gamma * st_scal[2] * sqrt(xx) + st_rho * st_scal[3] * sqrt(rr));
+            const bool diverged = !(rr <= 1e4 * st_scal[4]);
             if (stop || diverged) {
                 if (threadIdx.x == 0) {
-                    st.state[0] = 1;
+                    st_state[0] = 1;
                     if (diverged) atomicOr(status, ST_DIVERGED);
                 }
                 return;
             }
-        } else if (threadIdx.x == 0 && st.state[1] == 0) {
-            st.scal[4] = st.scal[0];                       // ||r(x_0)||^2
+        } else if (threadIdx.x == 0 && st_state[1] == 0) {
+            st_scal[4] = st_scal[0];                       // ||r(x_0)||^2
+        }
+        if (st_grow) {
+            const double rr = st_scal[0];
+            const bool first = st_state[1] == 0;
+            const int run = (!first && rr > st_scal[5] * (1.0 + 0x1p-20)) ? st_state[3] + 1 : 0;
+            if (run >= 3 || !isfinite(rr)) {
+                if (threadIdx.x == 0) {
+                    st_state[0] = 1;
+                    st_state[2] = 1;
+                }
+                return;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                st_state[3] = run;
+                st_scal[5] = rr;
+            }
         }
     }
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = c[j];
+    const int e = load_rhs<T>(n, c, s, red);
+    zero_pad<T, kSB>(n, s);
     __syncthreads();
-    fwd_subst<kSB>(n, R, ldr, s, L);
-    back_subst<kSB>(n, R, ldr, RT, s, L);
+    fwd_subst<T, kSB, kSolveThreads>(n, R, ldr, s, L);
+    back_subst<T, kSB, kSolveThreads>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        const double dj = s[j];
+        const double dj = (sizeof(T) == 8) ? (double)s[j] : ldexp((double)s[j], e);
         if (mode == 0) {
             dout[j] = dj;
             bad |= !isfinite(dj);
@@ -262,22 +558,22 @@ k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__re
             const double xo = x[j];
             const double xn = xo + dj;
             x[j] = xn;
-            if (st.state) st.dx[j] = xn - xo;
+            if (st_state) st_dx[j] = xn - xo;
             bad |= !isfinite(xn);
         } else {
             const double xo = x[j];
             const double xn = xo + alpha * dj + beta * (xo - xprev[j]);
             xprev[j] = xo;
             x[j] = xn;
-            if (st.state) st.dx[j] = xn - xo;
+            if (st_state) st_dx[j] = xn - xo;
             bad |= !isfinite(xn);
         }
     }
     if (bad) atomicOr(status, ST_NONFINITE);
-    if (st.state && threadIdx.x == 0) st.state[1] += 1;
+    if (st_state && threadIdx.x == 0) st_state[1] += 1;
 }
 
-// Section 3.3 estimators, one work-group.
+// Section 3.3 estimators, one work-group, in the arithmetic of the factor (T).
 //   normest: v = g/||g|| with g_i uniform on [-1, 1) (53 high bits of SplitMix64 output i of the
 //            stream `seed`); ceil(ln n) times: w = R v, est = ||w||, v = R^T w / ||R^T w||.
 //   condest: ||R||_1 times Hager's estimate of ||R^{-1}||_1 (Higham, Ch. 15): x = e/n; up to five
@@ -285,25 +581,26 @@ k_solve(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__re
 //            ||z||_inf <= z^T x, else x = e_j for the first j maximising |z_j|.
 constexpr int kEstThreads = 512;
 
-template <int kSB>
+template <typename T, int kSB>
 __global__ void __launch_bounds__(kEstThreads)
-k_estimators(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
-             uint64_t seed, double *__restrict__ work, double *__restrict__ scal)
+k_estimators(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT,
+             uint64_t seed, T *__restrict__ work, double *__restrict__ scal)
 {
-    extern __shared__ double s[];
-    __shared__ SubstLds<kSB> L;
-    __shared__ double red[kSolveThreads / 64];
-    __shared__ int64_t s_arg[kSolveThreads / 64];
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *s = reinterpret_cast<T *>(smem);
+    __shared__ SubstLds<T, kSB> L;
+    __shared__ T red[kEstThreads / 64];
+    __shared__ int64_t s_arg[kEstThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    double *v = work, *w = work + n, *xv = work + 2 * n;
+    T *v = work, *w = work + n, *xv = work + 2 * n;
     // ---- normest
-    double gg = 0.0;
+    T gg = T(0);
     for (int64_t i = tid; i < n; i += blockDim.x) {
         uint64_t z = seed + ((uint64_t)i + 1ULL) * 0x9E3779B97F4A7C15ULL;
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
         z ^= z >> 31;
-        const double g = 2.0 * ((double)(z >> 11) * 0x1p-53) - 1.0;
+        const T g = (T)(2.0 * ((double)(z >> 11) * 0x1p-53) - 1.0);
         v[i] = g;
         gg += g * g;
     }
@@ -312,35 +609,35 @@ k_estimators(int64_t n, const double *__restrict__ R, int64_t ldr, const double 
     __syncthreads();
     int steps = (int)ceil(log((double)n));
     if (steps < 1) steps = 1;
-    double est = 0.0;
+    T est = T(0);
     for (int it = 0; it < steps; ++it) {
         for (int64_t i = wave; i < n; i += nw) {            // w = R v, one row per wave
-            double a = 0.0;
+            T a = T(0);
             for (int64_t k = i + lane; k < n; k += 64) a += R[i * ldr + k] * v[k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
             if (lane == 0) w[i] = a;
         }
         __syncthreads();
-        double ww = 0.0;
+        T ww = T(0);
         for (int64_t i = tid; i < n; i += blockDim.x) ww += w[i] * w[i];
         est = sqrt(block_sum(ww, red));
-        double vv = 0.0;
+        T vv = T(0);
         for (int64_t k = tid; k < n; k += blockDim.x) {      // v = R^T w, one column per thread
-            double a = 0.0;
+            T a = T(0);
             for (int64_t i = 0; i <= k; ++i) a += R[i * ldr + k] * w[i];
             v[k] = a;
             vv += a * a;
         }
         vv = sqrt(block_sum(vv, red));
-        if (vv == 0.0) break;
+        if (vv == T(0)) break;
         for (int64_t k = tid; k < n; k += blockDim.x) v[k] /= vv;
         __syncthreads();
     }
     // ---- condest
-    double n1 = 0.0;
+    T n1 = T(0);
     for (int64_t k = tid; k < n; k += blockDim.x) {
-        double a = 0.0;
+        T a = T(0);
         for (int64_t i = 0; i <= k; ++i) a += fabs(R[i * ldr + k]);
         n1 = fmax(n1, a);
     }
@@ -349,25 +646,26 @@ k_estimators(int64_t n, const double *__restrict__ R, int64_t ldr, const double 
     __syncthreads();
     if (lane == 0) red[wave] = n1;
     __syncthreads();
-    n1 = 0.0;
+    n1 = T(0);
     for (int q = 0; q < nw; ++q) n1 = fmax(n1, red[q]);
-    for (int64_t i = tid; i < n; i += blockDim.x) xv[i] = 1.0 / (double)n;
+    for (int64_t i = tid; i < n; i += blockDim.x) xv[i] = T(1) / (T)n;
+    zero_pad<T, kSB>(n, s);
     __syncthreads();
-    double inv1 = 0.0;
+    T inv1 = T(0);
     for (int it = 0; it < 5; ++it) {
         for (int64_t i = tid; i < n; i += blockDim.x) s[i] = xv[i];
         __syncthreads();
-        back_subst<kSB>(n, R, ldr, RT, s, L);                 // y = R^{-1} x
-        double e1 = 0.0;
+        back_subst<T, kSB, kEstThreads, 1>(n, R, ldr, RT, s, L);     // y = R^{-1} x
+        T e1 = T(0);
         for (int64_t i = tid; i < n; i += blockDim.x) e1 += fabs(s[i]);
         inv1 = block_sum(e1, red);
-        for (int64_t i = tid; i < n; i += blockDim.x) s[i] = (s[i] >= 0.0) ? 1.0 : -1.0;
+        for (int64_t i = tid; i < n; i += blockDim.x) s[i] = (s[i] >= T(0)) ? T(1) : T(-1);
         __syncthreads();
-        fwd_subst<kSB>(n, R, ldr, s, L);                      // z = R^{-T} xi
-        double zmax = -1.0, ztx = 0.0;
+        fwd_subst<T, kSB, kEstThreads, 1>(n, R, ldr, s, L);          // z = R^{-T} xi
+        T zmax = T(-1), ztx = T(0);
         int64_t jmax = n;
         for (int64_t i = tid; i < n; i += blockDim.x) {
-            const double az = fabs(s[i]);
+            const T az = fabs(s[i]);
             if (az > zmax) { zmax = az; jmax = i; }
             ztx += s[i] * xv[i];
         }
@@ -375,61 +673,64 @@ k_estimators(int64_t n, const double *__restrict__ R, int64_t ldr, const double 
         // first index of the largest |z|: wave-level then block-level argmax
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            const double oz = __shfl_xor(zmax, off, 64);
+            const T oz = __shfl_xor(zmax, off, 64);
             const int64_t oj = __shfl_xor(jmax, off, 64);
             if (oz > zmax || (oz == zmax && oj < jmax)) { zmax = oz; jmax = oj; }
         }
         __syncthreads();
         if (lane == 0) { red[wave] = zmax; s_arg[wave] = jmax; }
         __syncthreads();
-        zmax = -1.0;
+        zmax = T(-1);
         jmax = n;
         for (int q = 0; q < nw; ++q)
             if (red[q] > zmax || (red[q] == zmax && s_arg[q] < jmax)) { zmax = red[q]; jmax = s_arg[q]; }
         __syncthreads();
         if (zmax <= ztx) break;
-        for (int64_t i = tid; i < n; i += blockDim.x) xv[i] = (i == jmax) ? 1.0 : 0.0;
+        for (int64_t i = tid; i < n; i += blockDim.x) xv[i] = (i == jmax) ? T(1) : T(0);
         __syncthreads();
     }
     if (tid == 0) {
-        scal[2] = est;
-        scal[3] = n1 * inv1;
+        scal[2] = (double)est;
+        scal[3] = (double)n1 * (double)inv1;
     }
 }
 
 __global__ void k_stop_init(int32_t *state)
 {
-    if (threadIdx.x < 2) state[threadIdx.x] = 0;
+    if (threadIdx.x < 4) state[threadIdx.x] = 0;
 }
 
-// x = R^{-1} y (sketch-and-solve start).
-template <int kSB>
+// x = R^{-1} y (sketch-and-solve start), y in the factor's type, x in FP64.
+template <typename T, int kSB>
 __global__ void __launch_bounds__(kSolveThreads)
-k_back(int64_t n, const double *__restrict__ R, int64_t ldr, const double *__restrict__ RT,
-       const double *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
+k_back(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT,
+       const T *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
 {
-    extern __shared__ double s[];
-    __shared__ SubstLds<kSB> L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *s = reinterpret_cast<T *>(smem);
+    __shared__ SubstLds<T, kSB> L;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = y[j];
+    zero_pad<T, kSB>(n, s);
     __syncthreads();
-    back_subst<kSB>(n, R, ldr, RT, s, L);
+    back_subst<T, kSB, kSolveThreads>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        x[j] = s[j];
+        x[j] = (double)s[j];
         bad |= !isfinite(s[j]);
     }
     if (bad) atomicOr(status, ST_NONFINITE);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_transpose(int64_t n, const double *__restrict__ R, int64_t ldr, double *__restrict__ RT)
+k_transpose(int64_t n, const T *__restrict__ R, int64_t ldr, T *__restrict__ RT)
 {
-    __shared__ double tile[32][33];
+    __shared__ T tile[32][33];
     const int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int64_t i = by + r, j = bx + tx;
-        tile[r][tx] = (i < n && j < n) ? ((j >= i) ? R[i * ldr + j] : 0.0) : 0.0;
+        tile[r][tx] = (i < n && j < n) ? ((j >= i) ? R[i * ldr + j] : T(0)) : T(0);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -438,15 +739,71 @@ k_transpose(int64_t n, const double *__restrict__ R, int64_t ldr, double *__rest
     }
 }
 
+// Rc = upper triangle of R with leading dimension n (zero below the diagonal).
+__global__ void __launch_bounds__(256)
+k_compact_upper(int64_t n, const double *__restrict__ R, int64_t ldr, double *__restrict__ Rc)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int64_t i = e / n, j = e % n;
+    Rc[e] = (j >= i) ? R[i * ldr + j] : 0.0;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T>
+hipError_t transpose_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, T *RT)
+{
+    hipLaunchKernelGGL(k_transpose<T>, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)),
+                       dim3(256), 0, s, n, R, ldr, RT);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t solve_update_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T *RT,
+                             const double *c, double *x, double *xprev, double *dout, int mode,
+                             double alpha, double beta, int32_t *status, const StopArgs &st)
+{
+    hipLaunchKernelGGL((k_solve<T, kSolveBlock>), dim3(1), dim3(kSolveThreads), (size_t)padded<kSolveBlock>(n) * sizeof(T), s, n, R,
+                       ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
+                       st.gamma, st.rho, st.check, st.grow);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t estimators_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T *RT,
+                           uint64_t seed, T *work, double *scal)
+{
+    hipLaunchKernelGGL((k_estimators<T, kSolveBlock>), dim3(1), dim3(kEstThreads), (size_t)padded<kSolveBlock>(n) * sizeof(T), s,
+                       n, R, ldr, RT, seed, work, scal);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t back_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T *RT, const T *y,
+                     double *x, int32_t *status)
+{
+    hipLaunchKernelGGL((k_back<T, kSolveBlock>), dim3(1), dim3(kSolveThreads), (size_t)padded<kSolveBlock>(n) * sizeof(T), s, n, R, ldr,
+                       RT, y, x, status);
+    return hipGetLastError();
+}
 
 }  // namespace
 
 hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT)
 {
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)),
-                       dim3(256), 0, s, n, R, ldr, RT);
+    return transpose_impl(s, n, R, ldr, RT);
+}
+
+hipError_t launch_compact_upper(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *Rc)
+{
+    hipLaunchKernelGGL(k_compact_upper, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, R, ldr, Rc);
     return hipGetLastError();
+}
+
+hipError_t launch_transpose(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *RT)
+{
+    return transpose_impl(s, n, R, ldr, RT);
 }
 
 hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_t ldr,
@@ -454,18 +811,27 @@ hipError_t launch_solve_update(hipStream_t s, int64_t n, const double *R, int64_
                                double *dout, int mode, double alpha, double beta, int32_t *status,
                                const StopArgs &st)
 {
-    hipLaunchKernelGGL(k_solve<kSolveBlock>, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R,
-                       ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
-                       st.gamma, st.rho, st.check);
-    return hipGetLastError();
+    return solve_update_impl(s, n, R, ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st);
+}
+
+hipError_t launch_solve_update(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                               const float *RT, const double *c, double *x, double *xprev,
+                               double *dout, int mode, double alpha, double beta, int32_t *status,
+                               const StopArgs &st)
+{
+    return solve_update_impl(s, n, R, ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st);
 }
 
 hipError_t launch_estimators(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                              const double *RT, uint64_t seed, double *work, double *scal)
 {
-    hipLaunchKernelGGL(k_estimators<kSolveBlock>, dim3(1), dim3(kEstThreads), (size_t)n * sizeof(double), s,
-                       n, R, ldr, RT, seed, work, scal);
-    return hipGetLastError();
+    return estimators_impl(s, n, R, ldr, RT, seed, work, scal);
+}
+
+hipError_t launch_estimators(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                             const float *RT, uint64_t seed, float *work, double *scal)
+{
+    return estimators_impl(s, n, R, ldr, RT, seed, work, scal);
 }
 
 hipError_t launch_stop_init(hipStream_t s, int32_t *state)
@@ -477,7 +843,11 @@ hipError_t launch_stop_init(hipStream_t s, int32_t *state)
 hipError_t launch_back_substitution(hipStream_t s, int64_t n, const double *R, int64_t ldr,
                                     const double *RT, const double *y, double *x, int32_t *status)
 {
-    hipLaunchKernelGGL(k_back<kSolveBlock>, dim3(1), dim3(kSolveThreads), (size_t)n * sizeof(double), s, n, R, ldr, RT, y,
-                       x, status);
-    return hipGetLastError();
+    return back_impl(s, n, R, ldr, RT, y, x, status);
+}
+
+hipError_t launch_back_substitution(hipStream_t s, int64_t n, const float *R, int64_t ldr,
+                                    const float *RT, const float *y, double *x, int32_t *status)
+{
+    return back_impl(s, n, R, ldr, RT, y, x, status);
 }
