@@ -1,6 +1,7 @@
 """CPU oracle for iterative sketching (test infrastructure).
 
-A plain FP64 C implementation (``ls_oracle.c``) of what the solver computes, loaded through ctypes.
+A plain C implementation (``ls_oracle.c``, FP64; FP32 only in the mixed-precision functions) of
+what the solver computes, loaded through ctypes.
 Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may import this
 package; the GPU library never does, and the two share no code.
 """
@@ -18,6 +19,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 _I8 = ctypes.POINTER(ctypes.c_int8)
 _i64 = ctypes.c_int64
@@ -73,12 +75,35 @@ def lib():
         L.orc_sketch_row.argtypes = [_i64, _i64, _D, _i64, _I8, _i32, _D]
         L.orc_dimension.restype = ctypes.c_int64
         L.orc_dimension.argtypes = [_i64, _i64, ctypes.c_double]
+        L.orc_solve_r_f32.restype = None
+        L.orc_solve_r_f32.argtypes = [_i64, _F, _i64, _F, _F]
+        L.orc_solve_rt_f32.restype = None
+        L.orc_solve_rt_f32.argtypes = [_i64, _F, _i64, _F, _F]
+        L.orc_householder_lstsq_f32.restype = ctypes.c_int
+        L.orc_householder_lstsq_f32.argtypes = [_i64, _i64, _F, _i64, _F, _F, _i64, _F, _D]
+        L.orc_precond_f32.restype = None
+        L.orc_precond_f32.argtypes = [_i64, _F, _i64, _D, _D]
+        L.orc_normest_f32.restype = ctypes.c_double
+        L.orc_normest_f32.argtypes = [_i64, _F, _i64, _D, _i32]
+        L.orc_condest_1_f32.restype = ctypes.c_double
+        L.orc_condest_1_f32.argtypes = [_i64, _F, _i64]
+        L.orc_iterative_sketching_mixed.restype = ctypes.c_int
+        L.orc_iterative_sketching_mixed.argtypes = [_i64, _i64, _D, _i64, _D, _i64, _i32, _u64, _i32,
+                                                    _D, _F, _i64, _D, ctypes.POINTER(ctypes.c_int32)]
         _lib = L
     return _lib
 
 
 def _dp(a):
     return None if a is None else a.ctypes.data_as(_D)
+
+
+def _fp(a):
+    return None if a is None else a.ctypes.data_as(_F)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
 
 
 def _f64(a):
@@ -247,3 +272,79 @@ def normest_start(n: int, seed: int):
         z = splitmix64(seed, i)
         out[i] = 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
     return out
+
+
+# ---- mixed precision (FP32 sketch, QR and solves; FP64 pass and update) -------------------------
+MIXED = 1            # the mixed path ran to the end
+FELL_BACK_COND = 2   # condest(R) u_32 > 0.05: redone in FP64
+FELL_BACK_GROWTH = 3 # ||r||^2 grew three steps in a row: redone in FP64
+
+
+def solve_r_f32(R, y):
+    R = _f32(R)
+    n = R.shape[0]
+    x = np.zeros(n, dtype=np.float32)
+    lib().orc_solve_r_f32(n, _fp(R), R.shape[1], _fp(_f32(y)), _fp(x))
+    return x
+
+
+def solve_rt_f32(R, c):
+    R = _f32(R)
+    n = R.shape[0]
+    y = np.zeros(n, dtype=np.float32)
+    lib().orc_solve_rt_f32(n, _fp(R), R.shape[1], _fp(_f32(c)), _fp(y))
+    return y
+
+
+def householder_lstsq_f32(M, rhs):
+    """Single-precision Householder QR of [M | rhs]: (x0 float64, R float32, Q^T rhs[:n] float32)."""
+    M = _f32(M)
+    rows, n = M.shape
+    R = np.zeros((n, n), dtype=np.float32)
+    qtb = np.zeros(n, dtype=np.float32)
+    x = np.zeros(n)
+    rc = lib().orc_householder_lstsq_f32(rows, n, _fp(M), n, _fp(_f32(rhs)), _fp(R), n, _fp(qtb), _dp(x))
+    if rc == 1:
+        raise ValueError("orc_householder_lstsq_f32: bad arguments")
+    if rc >= 3:
+        raise np.linalg.LinAlgError(f"rank deficient at column {rc - 3}")
+    if rc:
+        raise MemoryError("orc_householder_lstsq_f32")
+    return x, R, qtb
+
+
+def precond_f32(R, c):
+    """R^{-1} R^{-T} c with FP32 R and FP32 solves on c scaled by a power of two (FP64 in/out)."""
+    R = _f32(R)
+    n = R.shape[0]
+    d = np.zeros(n)
+    lib().orc_precond_f32(n, _fp(R), R.shape[1], _dp(_f64(c)), _dp(d))
+    return d
+
+
+def normest_f32(R, g, steps: int) -> float:
+    R = _f32(R)
+    return float(lib().orc_normest_f32(R.shape[0], _fp(R), R.shape[1], _dp(_f64(g)), steps))
+
+
+def condest_1_f32(R) -> float:
+    R = _f32(R)
+    return float(lib().orc_condest_1_f32(R.shape[0], _fp(R), R.shape[1]))
+
+
+def iterative_sketching_mixed(A, b, n: int, d: int, q: int, zeta: int = 8, seed: int = 0):
+    """Mixed-precision Algorithm 2 with the fallback rule: (x, used, R32, rnorm2 of mixed steps)."""
+    A, m, _, lda = _mat(A)
+    x = np.zeros(n)
+    R = np.zeros((n, n), dtype=np.float32)
+    rn = np.zeros(max(q, 1))
+    used = ctypes.c_int32(0)
+    rc = lib().orc_iterative_sketching_mixed(m, n, _dp(A), lda, _dp(_f64(b)), d, zeta, seed, q,
+                                             _dp(x), _fp(R), n, _dp(rn), ctypes.byref(used))
+    if rc == 1:
+        raise ValueError("orc_iterative_sketching_mixed: bad arguments")
+    if rc >= 3:
+        raise np.linalg.LinAlgError(f"sketch rank deficient at column {rc - 3}")
+    if rc:
+        raise MemoryError("orc_iterative_sketching_mixed")
+    return x, used.value, R, rn[:q]

@@ -7,7 +7,8 @@
  * benchmark load this library.  It shares no code, header or constant table with the GPU library;
  * the two meet only in the seeded input arrays they are both given.
  *
- * Everything is IEEE double, straight loops in the order the definitions state them, compiled
+ * Everything is IEEE double (single precision only in the mixed-precision functions at the end),
+ * straight loops in the order the definitions state them, compiled
  * with -ffp-contract=off so that no multiply-add is fused behind the reader's back.  Matrices are
  * row-major with an explicit leading dimension (elements between two rows).
  *
@@ -23,6 +24,11 @@
  *   orc_iterative_sketching Algorithm 2 end to end
  *   orc_iterative_sketching_dm  Algorithm 2 with damping / momentum, eq. (damping_momentum)
  *   orc_normest / orc_condest_1 / orc_dimension   Section 3.3 implementation guidance
+ *   orc_iterative_sketching_stop  Algorithm 2 with the Section 3.3 stopping rule
+ *   *_f32, orc_precond_f32, orc_iterative_sketching_mixed   the mixed-precision reading (single-
+ *                           precision sketch, QR and solves; double pass and update), with its
+ *                           fallback rule -- the paper is silent on precision; see the comment
+ *                           above these functions
  */
 #include <math.h>
 #include <stdint.h>
@@ -490,5 +496,243 @@ int orc_iterative_sketching_stop(int64_t m, int64_t n, const double *A, int64_t 
     }
 done:
     free(B); free(Sb); free(R); free(c); free(y); free(dv); free(xn);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Mixed precision.  The paper computes everything in double.  This is the reading in which the
+ * sketch is kept in single precision (the double sketch of orc_sketch, rounded once), its
+ * Householder QR and the two triangular solves of every step run in single precision, and the
+ * residual/gradient pass and the update stay in double, so the iteration is an iterative
+ * refinement whose preconditioner is a single-precision R.  Single-precision code below keeps every
+ * intermediate in IEEE binary32 (x86-64 SSE evaluates float expressions in float). */
+
+/* Back and forward substitution in single precision (as orc_solve_r / orc_solve_rt). */
+void orc_solve_r_f32(int64_t n, const float *R, int64_t ldr, const float *y, float *x)
+{
+    for (int64_t i = n - 1; i >= 0; --i) {
+        float s = y[i];
+        for (int64_t k = i + 1; k < n; ++k) s -= R[i * ldr + k] * x[k];
+        x[i] = s / R[i * ldr + i];
+    }
+}
+
+void orc_solve_rt_f32(int64_t n, const float *R, int64_t ldr, const float *c, float *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float s = c[i];
+        for (int64_t k = 0; k < i; ++k) s -= R[k * ldr + i] * y[k];
+        y[i] = s / R[i * ldr + i];
+    }
+}
+
+/* Householder-QR least squares in single precision: the steps of orc_householder_lstsq with every
+ * quantity a float (sigma by sqrtf of the float sum of squares).  x (double, nullable) receives the
+ * float back-substitution solution R x = (Q^T rhs)[0:n], widened.  Return codes as the double
+ * version. */
+int orc_householder_lstsq_f32(int64_t rows, int64_t n, const float *M, int64_t ldm, const float *rhs,
+                              float *R, int64_t ldr, float *qtb, double *x)
+{
+    if (n < 1 || rows < n || ldm < n || (R && ldr < n)) return 1;
+    int64_t w = n + 1;
+    float *W = (float *)malloc(sizeof(float) * (size_t)rows * (size_t)w);
+    float *v = (float *)malloc(sizeof(float) * (size_t)rows);
+    float *wt = (float *)malloc(sizeof(float) * (size_t)w);
+    float *Rl = (float *)malloc(sizeof(float) * (size_t)n * (size_t)n);
+    float *xs = (float *)malloc(sizeof(float) * (size_t)n);
+    if (!W || !v || !wt || !Rl || !xs) { free(W); free(v); free(wt); free(Rl); free(xs); return 2; }
+    for (int64_t i = 0; i < rows; ++i) {
+        for (int64_t c = 0; c < n; ++c) W[i * w + c] = M[i * ldm + c];
+        W[i * w + n] = rhs ? rhs[i] : 0.0f;
+    }
+    memset(Rl, 0, sizeof(float) * (size_t)n * (size_t)n);
+    int rc = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        float alpha = W[k * w + k];
+        float ss = 0.0f;
+        for (int64_t i = k; i < rows; ++i) ss += W[i * w + k] * W[i * w + k];
+        float sigma = sqrtf(ss);
+        if (sigma == 0.0f) { rc = 3 + (int)k; break; }
+        float beta = (alpha >= 0.0f) ? -sigma : sigma;
+        v[k] = alpha - beta;
+        for (int64_t i = k + 1; i < rows; ++i) v[i] = W[i * w + k];
+        float vtv = 0.0f;
+        for (int64_t i = k; i < rows; ++i) vtv += v[i] * v[i];
+        for (int64_t l = k + 1; l < w; ++l) wt[l] = 0.0f;
+        for (int64_t i = k; i < rows; ++i)
+            for (int64_t l = k + 1; l < w; ++l) wt[l] += v[i] * W[i * w + l];
+        for (int64_t l = k + 1; l < w; ++l) wt[l] = 2.0f * wt[l] / vtv;
+        for (int64_t i = k; i < rows; ++i)
+            for (int64_t l = k + 1; l < w; ++l) W[i * w + l] -= wt[l] * v[i];
+        Rl[k * n + k] = beta;
+        for (int64_t l = k + 1; l < n; ++l) Rl[k * n + l] = W[k * w + l];
+        W[k * w + k] = beta;
+        for (int64_t i = k + 1; i < rows; ++i) W[i * w + k] = 0.0f;
+    }
+    if (rc == 0) {
+        for (int64_t l = 0; l < n; ++l) wt[l] = W[l * w + n];
+        if (qtb) for (int64_t l = 0; l < n; ++l) qtb[l] = wt[l];
+        if (x) {
+            orc_solve_r_f32(n, Rl, n, wt, xs);
+            for (int64_t l = 0; l < n; ++l) x[l] = (double)xs[l];
+        }
+        if (R)
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t c = 0; c < n; ++c) R[i * ldr + c] = Rl[i * n + c];
+    }
+    free(W); free(v); free(wt); free(Rl); free(xs);
+    return rc;
+}
+
+/* d = R^{-1} (R^{-T} c) for a double c and a single-precision R: c is scaled by 2^-e, e the binary
+ * exponent of max_i |c_i| in the frexp convention (so the largest entry lands in [1/2, 1)), rounded
+ * to float, both substitutions run in float, and the result is scaled back by 2^e in double.  Both
+ * scalings are exact; the scaling keeps the float solves clear of underflow and overflow. */
+void orc_precond_f32(int64_t n, const float *R, int64_t ldr, const double *c, double *d)
+{
+    float *cs = (float *)malloc(sizeof(float) * (size_t)n);
+    float *y = (float *)malloc(sizeof(float) * (size_t)n);
+    float *z = (float *)malloc(sizeof(float) * (size_t)n);
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) if (fabs(c[i]) > mx) mx = fabs(c[i]);
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+    for (int64_t i = 0; i < n; ++i) cs[i] = (float)ldexp(c[i], -e);
+    orc_solve_rt_f32(n, R, ldr, cs, y);
+    orc_solve_r_f32(n, R, ldr, y, z);
+    for (int64_t i = 0; i < n; ++i) d[i] = ldexp((double)z[i], e);
+    free(cs); free(y); free(z);
+}
+
+/* Section 3.3 estimators evaluated in single precision on a single-precision R (the steps of
+ * orc_normest and orc_condest_1 with float quantities; the start vector g is rounded to float). */
+double orc_normest_f32(int64_t n, const float *R, int64_t ldr, const double *g, int32_t steps)
+{
+    float *v = (float *)malloc(sizeof(float) * (size_t)n);
+    float *w = (float *)malloc(sizeof(float) * (size_t)n);
+    float est = 0.0f, s = 0.0f;
+    for (int64_t i = 0; i < n; ++i) { v[i] = (float)g[i]; s += v[i] * v[i]; }
+    s = sqrtf(s);
+    for (int64_t i = 0; i < n; ++i) v[i] = v[i] / s;
+    for (int32_t it = 0; it < steps; ++it) {
+        float ww = 0.0f;
+        for (int64_t i = 0; i < n; ++i) {
+            float a = 0.0f;
+            for (int64_t k = i; k < n; ++k) a += R[i * ldr + k] * v[k];
+            w[i] = a;
+            ww += a * a;
+        }
+        est = sqrtf(ww);
+        float vv = 0.0f;
+        for (int64_t k = 0; k < n; ++k) {
+            float a = 0.0f;
+            for (int64_t i = 0; i <= k; ++i) a += R[i * ldr + k] * w[i];
+            v[k] = a;
+            vv += a * a;
+        }
+        vv = sqrtf(vv);
+        if (vv == 0.0f) break;
+        for (int64_t k = 0; k < n; ++k) v[k] /= vv;
+    }
+    free(v); free(w);
+    return (double)est;
+}
+
+double orc_condest_1_f32(int64_t n, const float *R, int64_t ldr)
+{
+    float n1 = 0.0f;
+    for (int64_t k = 0; k < n; ++k) {
+        float s = 0.0f;
+        for (int64_t i = 0; i <= k; ++i) s += fabsf(R[i * ldr + k]);
+        if (s > n1) n1 = s;
+    }
+    float *x = (float *)malloc(sizeof(float) * (size_t)n);
+    float *y = (float *)malloc(sizeof(float) * (size_t)n);
+    float *z = (float *)malloc(sizeof(float) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) x[i] = 1.0f / (float)n;
+    float est = 0.0f;
+    for (int it = 0; it < 5; ++it) {
+        orc_solve_r_f32(n, R, ldr, x, y);
+        est = 0.0f;
+        for (int64_t i = 0; i < n; ++i) est += fabsf(y[i]);
+        for (int64_t i = 0; i < n; ++i) y[i] = (y[i] >= 0.0f) ? 1.0f : -1.0f;
+        orc_solve_rt_f32(n, R, ldr, y, z);
+        int64_t jmax = 0;
+        float zmax = 0.0f, ztx = 0.0f;
+        for (int64_t i = 0; i < n; ++i) {
+            if (fabsf(z[i]) > zmax) { zmax = fabsf(z[i]); jmax = i; }
+            ztx += z[i] * x[i];
+        }
+        if (zmax <= ztx) break;
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0f;
+        x[jmax] = 1.0f;
+    }
+    free(x); free(y); free(z);
+    return (double)n1 * (double)est;
+}
+
+/* Algorithm 2 in mixed precision, with the fallback rule of this reading:
+ *   B, S b (double, orc_sketch) -> rounded to float; single-precision Householder QR gives R and
+ *   x_0; if condest(R) (orc_condest_1_f32) times u_32 = 2^-24 exceeds 0.05 (or is not finite), the
+ *   single-precision factor is not trusted and the whole solve is redone in double
+ *   (orc_iterative_sketching), *used = 2;
+ *   otherwise q steps x <- x + orc_precond_f32(R, A^T (b - A x)) with the pass and the update in
+ *   double; if ||r(x_i)||^2 grows three steps in a row, each time by more than a relative 2^-20
+ *   (well above its rounding noise), or is not finite, the solve is redone in double, *used = 3;
+ *   else *used = 1.
+ * R_out (nullable, float, ldr) receives the single-precision R; rnorm2_hist (nullable, q) the
+ * ||r_i||^2 of the mixed steps made.  Return codes as orc_iterative_sketching. */
+int orc_iterative_sketching_mixed(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                                  int64_t d, int32_t zeta, uint64_t seed, int32_t q, double *x,
+                                  float *R_out, int64_t ldr, double *rnorm2_hist, int32_t *used)
+{
+    if (n < 1 || m < n || d < n || q < 0 || lda < n) return 1;
+    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)n);
+    double *Sb = (double *)malloc(sizeof(double) * (size_t)d);
+    float *B32 = (float *)malloc(sizeof(float) * (size_t)d * (size_t)n);
+    float *Sb32 = (float *)malloc(sizeof(float) * (size_t)d);
+    float *R = (float *)malloc(sizeof(float) * (size_t)n * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dv = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 2;
+    *used = 1;
+    if (!B || !Sb || !B32 || !Sb32 || !R || !c || !dv) goto done;
+    rc = orc_sketch(m, n, A, lda, b, d, zeta, seed, B, n, Sb);
+    if (rc) goto done;
+    for (int64_t i = 0; i < d * n; ++i) B32[i] = (float)B[i];
+    for (int64_t i = 0; i < d; ++i) Sb32[i] = (float)Sb[i];
+    rc = orc_householder_lstsq_f32(d, n, B32, n, Sb32, R, n, NULL, x);
+    if (rc) goto done;
+    if (R_out)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t l = 0; l < n; ++l) R_out[i * ldr + l] = R[i * n + l];
+    {
+        double ce = orc_condest_1_f32(n, R, n);
+        if (!(ce * ldexp(1.0, -24) <= 0.05)) {
+            *used = 2;
+            rc = orc_iterative_sketching(m, n, A, lda, b, d, zeta, seed, q, x, NULL, NULL, 0, NULL);
+            goto done;
+        }
+    }
+    {
+        double prev = 0.0;
+        int run = 0;
+        for (int32_t i = 0; i < q; ++i) {
+            double rr;
+            orc_residual_gradient(m, n, A, lda, b, x, c, &rr);
+            if (rnorm2_hist) rnorm2_hist[i] = rr;
+            run = (i >= 1 && rr > prev * (1.0 + ldexp(1.0, -20))) ? run + 1 : 0;
+            if (run >= 3 || !isfinite(rr)) {
+                *used = 3;
+                rc = orc_iterative_sketching(m, n, A, lda, b, d, zeta, seed, q, x, NULL, NULL, 0, NULL);
+                goto done;
+            }
+            prev = rr;
+            orc_precond_f32(n, R, n, c, dv);
+            for (int64_t l = 0; l < n; ++l) x[l] = x[l] + dv[l];
+        }
+    }
+done:
+    free(B); free(Sb); free(B32); free(Sb32); free(R); free(c); free(dv);
     return rc;
 }

@@ -470,3 +470,138 @@ def test_normest_start_is_uniform():
     g = oracle.normest_start(20000, 5)
     assert -1.0 <= g.min() and g.max() < 1.0
     assert abs(g.mean()) < 0.02 and abs(g.var() - 1.0 / 3.0) < 0.01
+
+
+# ---------------------------------------------------------------- mixed precision -----------
+# The paper runs in FP64 only; the mixed-precision reading (FP32 sketch, QR and solves, FP64 pass
+# and update, with a fallback to FP64) is pinned by exact small cases, LAPACK's single-precision QR,
+# power-of-two scaling identities and the convergence of refinement to FP64 accuracy.
+U32 = 2.0 ** -24
+
+
+def test_f32_qr_exact_case_and_sign_convention():
+    # orthogonal columns with integer norms: R is exact in float, beta = -sign(alpha) sigma with
+    # sign(0) = +1 (second column's pivot is 0 after the first reflection)
+    M = np.array([[3, 0], [4, 0], [0, 5]], dtype=np.float32)
+    x, R, qtb = oracle.householder_lstsq_f32(M, np.array([1, 2, 3], dtype=np.float32))
+    assert R.dtype == np.float32
+    assert np.array_equal(R, np.array([[-5, 0], [0, -5]], dtype=np.float32))
+    # the least-squares solution is (M^T M)^{-1} M^T rhs = (11, 15) / 25 exactly; float arithmetic
+    # puts it within a few u_32 of that, and not within FP64 rounding (it is not a double solve)
+    exact = np.array([0.44, 0.6])
+    assert np.all(np.abs(x - exact) <= 8 * U32 * exact)
+    assert np.abs(x - exact).max() > 1e-12
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e3])
+def test_f32_qr_backward_error_and_lapack(kappa):
+    rng = np.random.default_rng(5)
+    rows, n = 400, 24
+    U_, _ = np.linalg.qr(rng.standard_normal((rows, n)))
+    V_, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    M = ((U_ * np.logspace(0, -np.log10(kappa), n)) @ V_.T).astype(np.float32)
+    rhs = rng.standard_normal(rows).astype(np.float32)
+    _, R, _ = oracle.householder_lstsq_f32(M, rhs)
+    M64, R64 = M.astype(np.float64), R.astype(np.float64)
+    err = np.linalg.norm(R64.T @ R64 - M64.T @ M64)
+    scale = np.linalg.norm(M64) ** 2
+    assert err <= 4 * n * U32 * scale            # backward stable at single precision
+    assert err >= 1e-3 * U32 * scale              # ... and really computed in single precision
+    # LAPACK's single-precision QR agrees up to the signs of R's rows, within kappa u_32
+    Rl = np.linalg.qr(M, mode="r").astype(np.float64)
+    sg = np.sign(np.diag(R64)) * np.sign(np.diag(Rl))
+    assert np.linalg.norm(R64 - sg[:, None] * Rl) <= 50 * kappa * n * U32 * np.linalg.norm(R64)
+
+
+def test_f32_triangular_solves_integer_exact():
+    rng = np.random.default_rng(2)
+    n = 12
+    R = np.triu(rng.integers(-2, 3, (n, n))).astype(np.float64)
+    np.fill_diagonal(R, 1.0)
+    y = rng.integers(-3, 4, n).astype(np.float64)
+    Rf = [[Fraction(int(v)) for v in row] for row in R]
+    # exact solutions by rational substitution; integers small enough to be exact in float
+    xr = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        xr[i] = Fraction(int(y[i])) - sum(Rf[i][k] * xr[k] for k in range(i + 1, n))
+    yr = [Fraction(0)] * n
+    for i in range(n):
+        yr[i] = Fraction(int(y[i])) - sum(Rf[k][i] * yr[k] for k in range(i))
+    assert max(abs(v) for v in xr + yr) < 2 ** 24
+    assert np.array_equal(oracle.solve_r_f32(R, y), np.array([float(v) for v in xr], dtype=np.float32))
+    assert np.array_equal(oracle.solve_rt_f32(R, y), np.array([float(v) for v in yr], dtype=np.float32))
+
+
+def test_precond_f32_power_of_two_scaling():
+    rng = np.random.default_rng(9)
+    n = 40
+    R = np.triu(rng.standard_normal((n, n))) / np.sqrt(n)
+    np.fill_diagonal(R, 1.0 + rng.random(n))
+    R32 = R.astype(np.float32)
+    c = rng.standard_normal(n)
+    d0 = oracle.precond_f32(R32, c)
+    # the right-hand side is rescaled by an exact power of two, so scaling c scales d exactly --
+    # also where unscaled float arithmetic would underflow (2^-600) or overflow (2^600)
+    for k in [-1000, -600, -100, 0, 50, 600]:
+        assert np.array_equal(oracle.precond_f32(R32, np.ldexp(c, k)), np.ldexp(d0, k))
+    assert np.array_equal(oracle.precond_f32(R32, np.zeros(n)), np.zeros(n))
+    # against the FP64 solves with the same (float) factor: single-precision accuracy
+    R64 = R32.astype(np.float64)
+    d64 = scipy.linalg.solve_triangular(R64, scipy.linalg.solve_triangular(R64.T, c, lower=True))
+    rel = np.linalg.norm(d0 - d64) / np.linalg.norm(d64)
+    assert rel <= 20 * n * np.linalg.cond(R64) * U32
+    assert rel >= 1e-12                                   # single precision, not double
+
+
+def test_estimators_f32():
+    rng = np.random.default_rng(4)
+    n = 30
+    U_, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    R = np.linalg.qr((U_ * np.logspace(0, -3, n)) @ np.linalg.qr(rng.standard_normal((n, n)))[0].T, mode="r")
+    R32 = R.astype(np.float32)
+    R64 = R32.astype(np.float64)
+    k1 = np.linalg.norm(R64, 1) * np.linalg.norm(np.linalg.inv(R64), 1)
+    ce = oracle.condest_1_f32(R32)
+    assert k1 / 20 <= ce <= k1 * (1 + 1e-3)
+    assert abs(ce - oracle.condest_1(R64)) <= 1e-3 * ce
+    g = oracle.normest_start(n, 3)
+    steps = int(math.ceil(math.log(n)))
+    ne = oracle.normest_f32(R32, g, steps)
+    assert abs(ne - oracle.normest(R64, g, steps)) <= 1e-5 * ne
+    assert ne <= np.linalg.norm(R64, 2) * (1 + 1e-5)
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e3, 1e5])
+def test_mixed_refinement_reaches_fp64_accuracy(kappa):
+    spec = ProblemSpec(m=4000, n=50, kappa=kappa, beta=1e-6, d=1000, seed=1)
+    p = make_problem_cpu(spec)
+    x, used, R32, rn = oracle.iterative_sketching_mixed(p.A, p.b, 50, 1000, 60, seed=spec.sketch_seed)
+    assert used == oracle.MIXED
+    fe_h = np.linalg.norm(oracle.householder_lstsq(p.Aview, p.b)[0] - p.x_true)
+    assert np.linalg.norm(x - p.x_true) <= 10 * fe_h     # FP64 accuracy from an FP32 factor
+    # the FP32 sketch-and-solve start alone is only single-precision accurate
+    x0, _, _ = oracle.householder_lstsq_f32(*oracle.sketch(p.A, p.b, 50, 1000, 8, spec.sketch_seed))
+    assert np.linalg.norm(x0 - p.x_true) >= 100 * fe_h
+    # ||r_i||^2 is non-increasing up to rounding (the monitor never fired)
+    assert np.all(rn[1:] <= rn[:-1] * (1 + 2.0 ** -20))
+
+
+def test_mixed_falls_back_when_condest_too_large():
+    spec = ProblemSpec(m=4000, n=50, kappa=1e12, beta=1e-6, d=1000, seed=1)
+    p = make_problem_cpu(spec)
+    x, used, R32, _ = oracle.iterative_sketching_mixed(p.A, p.b, 50, 1000, 30, seed=spec.sketch_seed)
+    assert used == oracle.FELL_BACK_COND
+    assert oracle.condest_1_f32(R32) * U32 > 0.05
+    assert np.array_equal(x, oracle.iterative_sketching(p.A, p.b, 50, 1000, 30, seed=spec.sketch_seed))
+
+
+def test_mixed_growth_monitor_falls_back():
+    # d = n leaves S far from an embedding: the iteration diverges (Theorem 3.1 needs distortion
+    # below 0.29) although the FP32 factor itself is well conditioned
+    spec = ProblemSpec(m=2000, n=20, kappa=1e3, beta=1e-3, d=20, seed=0)
+    p = make_problem_cpu(spec)
+    x, used, R32, rn = oracle.iterative_sketching_mixed(p.A, p.b, 20, 20, 40, seed=spec.sketch_seed)
+    assert used == oracle.FELL_BACK_GROWTH
+    assert oracle.condest_1_f32(R32) * U32 <= 0.05
+    assert rn[1] > rn[0] and rn[2] > rn[1] and rn[3] > rn[2]
+    assert np.array_equal(x, oracle.iterative_sketching(p.A, p.b, 20, 20, 40, seed=spec.sketch_seed))
