@@ -65,7 +65,7 @@ enum {
     LS_OPT_UPDATE = 3,      /* 0: x += d (Alg. 2); 1: damping; 2: momentum (eq. damping_momentum) */
     LS_OPT_ALPHA = 4,       /* alpha of the damping/momentum update (dval; <= 0: from eps)      */
     LS_OPT_BETA = 5,        /* beta of the momentum update (dval; < 0: from eps)                */
-    LS_OPT_PRECISION = 6,   /* 0: FP64 throughout; 1: sketch, QR and R-solves in FP32           */
+    LS_OPT_PRECISION = 6,   /* 0: FP64 throughout; 1: mixed (see "Mixed precision" below)        */
     LS_OPT_PROFILE = 7,     /* 1: time every launch of the fused pass kernel with HIP events    */
     LS_OPT_QR_PANEL = 8,    /* 0: one cooperative launch per QR panel when the device allows it;
                                1: one launch per column (the fallback path)                     */
@@ -148,14 +148,51 @@ ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doub
  * ||R||_1 times Hager's estimate of ||R^{-1}||_1.  The decision is taken on the device; a residual
  * that grows past 100 ||r(x_0)|| ends the iteration with LS_ERR_DIVERGED.
  * Enqueues sketch, QR and iterations, then waits on `stream` and returns the deferred status (as
- * ls_sync).  Requires d >= n and the limits above. */
+ * ls_sync).  With LS_OPT_PRECISION = 1 it also waits once after the QR, to take the fallback
+ * decision described under "Mixed precision".  Requires d >= n and the limits above. */
 ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
                    const double *b, int64_t d, int32_t q, double *x);
 
-/* After ls_solve: the embedding dimension used, the number of refinement steps made, and (with
- * LS_OPT_STOP = 1) normest and condest (NaN otherwise).  Any pointer may be NULL. */
+/* After ls_solve: the embedding dimension used, the number of refinement steps made (those of the
+ * FP64 solve after a fallback), normest and condest when they were computed (LS_OPT_STOP = 1 or
+ * LS_OPT_PRECISION = 1; NaN otherwise; from the FP32 factor on the mixed path), and the precision
+ * the result came from (LS_PRECISION_*).  Any pointer may be NULL. */
 ls_status ls_solve_info(ls_ctx *ctx, int64_t *d_used, int32_t *steps, double *normest,
-                        double *condest);
+                        double *condest, int32_t *precision);
+
+/* ---- Mixed precision (LS_OPT_PRECISION = 1) ------------------------------------------------------
+ * The paper computes in FP64 only.  In this variant the sketch is stored in FP32 (each entry of the
+ * FP64 sum rounded once), its Householder QR runs in FP32 (trailing updates on FP32 matrix cores),
+ * and the two triangular solves of every step run in FP32 on c scaled by 2^-e, e the binary
+ * exponent of max |c_i| (frexp convention), with d scaled back exactly in FP64; the A^T (b - A x)
+ * pass and the update stay FP64, so the refinement still reaches FP64 accuracy when the FP32 factor
+ * is a usable preconditioner.  ls_solve falls back to the FP64 solve, from the start, when
+ *   condest(R) * 2^-24 > 0.05 (condest in FP32 arithmetic on the FP32 R), or the FP32 QR flags R
+ *   as rank deficient or non-finite                                   -> LS_PRECISION_FELL_BACK_COND
+ *   ||r_i||^2 grows three steps in a row, each time by more than a relative 2^-20, or is not
+ *   finite                                                            -> LS_PRECISION_FELL_BACK_GROWTH
+ * The pieces are exposed for testing: */
+#define LS_PRECISION_FP64 0
+#define LS_PRECISION_MIXED 1
+#define LS_PRECISION_FELL_BACK_COND 2
+#define LS_PRECISION_FELL_BACK_GROWTH 3
+
+/* ls_sketch with FP32 outputs: B (d x n, ldb >= n) and Sb (d, nullable with b) are the FP64 sums of
+ * ls_sketch rounded once to FP32.  B and Sb must be 4-byte aligned. */
+ls_status ls_sketch_f32(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                        const double *b, int64_t d, int32_t zeta, uint64_t seed, float *B, int64_t ldb,
+                        float *Sb);
+
+/* ls_qr_sketch in FP32: R (n x n, FP32, ldr >= n, zero strict lower triangle) and x0 (FP64,
+ * nullable) = the FP32 back substitution R^{-1} (Q^T Sb)[0:n], widened.  Deferred: LS_ERR_RANK if
+ * |R_kk| <= n 2^-24 max|R_jj|; LS_ERR_NONFINITE.  B, Sb, R must be 4-byte aligned. */
+ls_status ls_qr_sketch_f32(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const float *B,
+                           int64_t ldb, const float *Sb, float *R, int64_t ldr, double *x0);
+
+/* d = R^{-1} (R^{-T} c) with an FP32 R (4-byte aligned, ldr >= n) by FP32 substitution on c scaled
+ * by a power of two as above; c and d are FP64. */
+ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float *R, int64_t ldr,
+                               const double *c, double *d);
 
 /* Waits for `stream`, then returns and clears the deferred device status of the context. */
 ls_status ls_sync(ls_ctx *ctx, void *stream);

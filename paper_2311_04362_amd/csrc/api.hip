@@ -39,18 +39,20 @@ ls_status check_embedding(ls_ctx *ctx, int64_t m, int64_t d, int32_t zeta)
     return LS_OK;
 }
 
-ls_status check_mat(ls_ctx *ctx, const void *p, int64_t ld, int64_t n, const char *name)
+ls_status check_mat(ls_ctx *ctx, const void *p, int64_t ld, int64_t n, const char *name, size_t align = 8)
 {
     if (!p) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is NULL");
-    if (!aligned(p, 8)) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+    if (!aligned(p, align))
+        return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not " + std::to_string(align) + "-byte aligned");
     if (ld < n) return ls_fail(ctx, LS_ERR_ARG, std::string("leading dimension of ") + name + " < n");
     return LS_OK;
 }
 
-ls_status check_vec(ls_ctx *ctx, const void *p, const char *name, bool nullable = false)
+ls_status check_vec(ls_ctx *ctx, const void *p, const char *name, bool nullable = false, size_t align = 8)
 {
     if (!p) return nullable ? LS_OK : ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is NULL");
-    if (!aligned(p, 8)) return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not 8-byte aligned");
+    if (!aligned(p, align))
+        return ls_fail(ctx, LS_ERR_ARG, std::string(name) + " is not " + std::to_string(align) + "-byte aligned");
     return LS_OK;
 }
 
@@ -205,6 +207,150 @@ ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes)
     return LS_OK;
 }
 
+// Algorithm 2 in FP64 (the body of ls_solve; also the fallback of the mixed path).
+static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
+                     const double *b, int64_t d, int32_t q, double *x)
+{
+    const int32_t zeta = ctx->zeta;
+    SketchBufs sb{};
+    QrBufs qb{};
+    IterBufs ib{};
+    double *R = nullptr, *est_work = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        sketch_bufs(ar, m, d, zeta, sb);
+        qr_bufs(ar, d, n, qb);
+        iter_bufs(ar, m, n, ib, false);
+        R = ar.take<double>((size_t)n * (size_t)n);
+        est_work = ar.take<double>((size_t)3 * (size_t)n);
+    }));
+    // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
+    const double scale = 1.0 / std::sqrt((double)zeta);
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
+    // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
+    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
+    HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
+    // (c) q refinement steps (with the stopping rule: at most q, ended on the device).
+    int mode;
+    double alpha, beta;
+    update_params(ctx, n, d, mode, alpha, beta);
+    StopArgs st;
+    if (ctx->stop) {
+        HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+        HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
+        st.state = ib.state;
+        st.scal = ib.scal;
+        st.dx = ib.dx;
+        st.gamma = ctx->gamma;
+        st.rho = ctx->rho;
+    }
+    if (mode == 2 && q > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
+    for (int32_t i = 0; i < q; ++i) {
+        if (ctx->stop) {
+            st.check = (i >= 1);
+            hipEvent_t e0, e1;
+            LS_TRY(pass_events(ctx, e0, e1));
+            HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
+                                         i >= 1 ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
+        } else {
+            LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
+        }
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
+    }
+    const ls_status status = ls_sync(ctx, s);
+    if (ctx->stop) {
+        int32_t stv[2];
+        double scv[4];
+        HIP_TRY(ctx, hipMemcpy(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost), "read steps");
+        HIP_TRY(ctx, hipMemcpy(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost), "read estimates");
+        ctx->last_steps = stv[1];
+        ctx->last_normest = scv[2];
+        ctx->last_condest = scv[3];
+    }
+    return status;
+}
+
+
+// Algorithm 2 with the FP32 sketch, QR and R-solves of the mixed-precision variant (the A^T (b-Ax)
+// pass and the update stay FP64).  Sets `used` to LS_PRECISION_MIXED when x is final, or to a
+// fallback reason, in which case the caller redoes the solve in FP64.  Waits on the stream after
+// the QR and the estimators (the fallback decision needs condest on the host) and at the end.
+static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
+                      const double *b, int64_t d, int32_t q, double *x, int32_t &used)
+{
+    const int32_t zeta = ctx->zeta;
+    SketchBufs sb{};
+    QrBufs32 qb{};
+    IterBufs ib{};
+    float *R = nullptr, *est_work = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        sketch_bufs(ar, m, d, zeta, sb);
+        qr_bufs(ar, d, n, qb);
+        iter_bufs(ar, m, n, ib, false);
+        R = ar.take<float>((size_t)n * (size_t)n);
+        est_work = ar.take<float>((size_t)3 * (size_t)n);
+    }));
+    // (a) FP32 sketch straight into the QR work matrix (FP64 sums, rounded once).
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
+    const double scale = 1.0 / std::sqrt((double)zeta);
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
+    // (b) FP32 QR, R, x0 by FP32 back substitution (widened), FP32 estimators.
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
+    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
+    HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
+    HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+    double scv[4];
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status");
+    HIP_TRY(ctx, hipMemcpyAsync(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost, s), "read estimates");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+    ctx->last_normest = scv[2];
+    ctx->last_condest = scv[3];
+    const int32_t st0 = *ctx->status_host;
+    if ((st0 & (ST_RANK | ST_NONFINITE)) || !(scv[3] * 0x1p-24 <= 0.05)) {
+        if (st0 != 0) {
+            HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
+            HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+        }
+        used = LS_PRECISION_FELL_BACK_COND;
+        return LS_OK;
+    }
+    // (c) q refinement steps: FP64 pass, FP32 solves, FP64 update, growth monitor on the device.
+    int mode;
+    double alpha, beta;
+    update_params(ctx, n, d, mode, alpha, beta);
+    HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
+    StopArgs st;
+    st.state = ib.state;
+    st.scal = ib.scal;
+    st.dx = ib.dx;
+    st.gamma = ctx->gamma;
+    st.rho = ctx->rho;
+    st.grow = 1;
+    if (mode == 2 && q > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
+    for (int32_t i = 0; i < q; ++i) {
+        const bool check = ctx->stop && i >= 1;
+        st.check = check;
+        hipEvent_t e0, e1;
+        LS_TRY(pass_events(ctx, e0, e1));
+        HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
+                                     check ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
+    }
+    int32_t stv[4];
+    HIP_TRY(ctx, hipMemcpyAsync(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost, s), "read steps");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+    ctx->last_steps = stv[1];
+    if (stv[2]) {                      // the FP64 solve starts from a clean status word
+        used = LS_PRECISION_FELL_BACK_GROWTH;
+        HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
+        HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
+    }
+    return LS_OK;
+}
+
 extern "C" {
 
 ls_status ls_limits(int32_t *max_zeta, int32_t *max_n)
@@ -286,8 +432,8 @@ ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval)
         ctx->beta = dval;
         return LS_OK;
     case LS_OPT_PRECISION:
-        if (ival != 0) return ls_fail(ctx, LS_ERR_UNSUPPORTED, "only FP64 (precision 0) is built");
-        ctx->precision = 0;
+        if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "precision must be 0 (FP64) or 1 (mixed)");
+        ctx->precision = (int32_t)ival;
         return LS_OK;
     case LS_OPT_PROFILE:
         if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "profile must be 0 or 1");
@@ -460,6 +606,73 @@ ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R
     return LS_OK;
 }
 
+ls_status ls_sketch_f32(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
+                        const double *b, int64_t d, int32_t zeta, uint64_t seed, float *B, int64_t ldb,
+                        float *Sb)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    LS_TRY(check_embedding(ctx, m, d, zeta));
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_mat(ctx, B, ldb, n, "B", 4));
+    if ((b == nullptr) != (Sb == nullptr)) return ls_fail(ctx, LS_ERR_ARG, "b and Sb must both be given or both NULL");
+    LS_TRY(check_vec(ctx, b, "b", true));
+    LS_TRY(check_vec(ctx, Sb, "Sb", true, 4));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SketchBufs sb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, true));
+    const double scale = 1.0 / std::sqrt((double)zeta);
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1), "gather kernel");
+    return LS_OK;
+}
+
+ls_status ls_qr_sketch_f32(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const float *B,
+                           int64_t ldb, const float *Sb, float *R, int64_t ldr, double *x0)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
+    LS_TRY(check_mat(ctx, B, ldb, n, "B", 4));
+    LS_TRY(check_vec(ctx, Sb, "Sb", false, 4));
+    LS_TRY(check_mat(ctx, R, ldr, n, "R", 4));
+    LS_TRY(check_vec(ctx, x0, "x0", true));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    QrBufs32 qb{};
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb); }));
+    HIP_TRY(ctx, launch_copy_sketch(s, d, n, B, ldb, Sb, qb), "copy sketch");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
+    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, ldr, ctx->status), "extract R");
+    if (x0) HIP_TRY(ctx, launch_back_substitution(s, n, (const float *)R, ldr, qb.RT, qb.qtb, x0, ctx->status), "x0 solve");
+    return LS_OK;
+}
+
+ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float *R, int64_t ldr,
+                               const double *c, double *d)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    LS_TRY(check_mat(ctx, R, ldr, n, "R", 4));
+    LS_TRY(check_vec(ctx, c, "c"));
+    LS_TRY(check_vec(ctx, d, "d"));
+    LS_TRY(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *RT = nullptr, *Rc = nullptr;
+    LS_TRY(with_arena(ctx, [&](Arena &ar) {
+        RT = ar.take<float>((size_t)n * (size_t)n);
+        Rc = ar.take<float>((size_t)n * (size_t)n);
+    }));
+    HIP_TRY(ctx, launch_transpose(s, n, R, ldr, RT), "transpose R");
+    HIP_TRY(ctx, launch_compact_upper(s, n, R, ldr, Rc), "compact R");
+    HIP_TRY(ctx, launch_solve_update(s, n, (const float *)Rc, n, (const float *)RT, c, nullptr, nullptr, d, 0, 0.0, 0.0, ctx->status), "solve kernel");
+    return LS_OK;
+}
+
 ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
                      const double *b, const double *R, int64_t ldr, double *x, int32_t q,
                      double *rnorm2)
@@ -509,81 +722,33 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     if (d <= 0) d = dimension_rule(m, n);
     if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
     if (q < 0) return ls_fail(ctx, LS_ERR_ARG, "q must be >= 0");
-    const int32_t zeta = ctx->zeta;
-    LS_TRY(check_embedding(ctx, m, d, zeta));
+    LS_TRY(check_embedding(ctx, m, d, ctx->zeta));
     LS_TRY(check_mat(ctx, A, lda, n, "A"));
     LS_TRY(check_vec(ctx, b, "b"));
     LS_TRY(check_vec(ctx, x, "x"));
     LS_TRY(need_device(ctx));
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SketchBufs sb{};
-    QrBufs qb{};
-    IterBufs ib{};
-    double *R = nullptr, *est_work = nullptr;
-    LS_TRY(with_arena(ctx, [&](Arena &ar) {
-        sketch_bufs(ar, m, d, zeta, sb);
-        qr_bufs(ar, d, n, qb);
-        iter_bufs(ar, m, n, ib, false);
-        R = ar.take<double>((size_t)n * (size_t)n);
-        est_work = ar.take<double>((size_t)3 * (size_t)n);
-    }));
     ctx->last_d = d;
     ctx->last_q = q;
     ctx->last_steps = q;
     ctx->last_normest = ctx->last_condest = NAN;
-    // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
-    LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
-    const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
-    // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
-    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
-    HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
-    // (c) q refinement steps (with the stopping rule: at most q, ended on the device).
-    int mode;
-    double alpha, beta;
-    update_params(ctx, n, d, mode, alpha, beta);
-    StopArgs st;
-    if (ctx->stop) {
-        HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
-        HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
-        st.state = ib.state;
-        st.scal = ib.scal;
-        st.dx = ib.dx;
-        st.gamma = ctx->gamma;
-        st.rho = ctx->rho;
+    ctx->last_precision = LS_PRECISION_FP64;
+    if (ctx->precision == 1) {
+        int32_t used = LS_PRECISION_MIXED;
+        LS_TRY(solve_mixed(ctx, s, m, n, A, lda, b, d, q, x, used));
+        ctx->last_precision = used;
+        if (used == LS_PRECISION_MIXED) return ls_sync(ctx, stream);
+        ctx->last_steps = q;
     }
-    if (mode == 2 && q > 0)
-        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
-    for (int32_t i = 0; i < q; ++i) {
-        if (ctx->stop) {
-            st.check = (i >= 1);
-            hipEvent_t e0, e1;
-            LS_TRY(pass_events(ctx, e0, e1));
-            HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
-                                         i >= 1 ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
-        } else {
-            LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
-        }
-        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
-    }
-    const ls_status status = ls_sync(ctx, stream);
-    if (ctx->stop) {
-        int32_t stv[2];
-        double scv[4];
-        HIP_TRY(ctx, hipMemcpy(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost), "read steps");
-        HIP_TRY(ctx, hipMemcpy(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost), "read estimates");
-        ctx->last_steps = stv[1];
-        ctx->last_normest = scv[2];
-        ctx->last_condest = scv[3];
-    }
-    return status;
+    return solve_fp64(ctx, s, m, n, A, lda, b, d, q, x);
 }
 
-ls_status ls_solve_info(ls_ctx *ctx, int64_t *d_used, int32_t *steps, double *normest, double *condest)
+ls_status ls_solve_info(ls_ctx *ctx, int64_t *d_used, int32_t *steps, double *normest, double *condest,
+                        int32_t *precision)
 {
     if (!ctx) return LS_ERR_ARG;
+    if (precision) *precision = ctx->last_precision;
     if (d_used) *d_used = ctx->last_d;
     if (steps) *steps = ctx->last_steps;
     if (normest) *normest = ctx->last_normest;

@@ -21,7 +21,7 @@ struct ls_ctx {
     int32_t update = 0;             // 0 plain, 1 damping, 2 momentum
     double alpha = 0.0;             // <= 0: derived from eps = sqrt(n/d)
     double beta = -1.0;             // < 0: derived from eps
-    int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves)
+    int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves, FP64 pass/update)
     int32_t profile = 0;            // 1: bracket each fused-pass launch with events
     int32_t qr_panel = 0;           // 1: force the per-column panel path
     int32_t stop = 0;               // 1: Section 3.3 stopping rule in ls_solve
@@ -31,6 +31,7 @@ struct ls_ctx {
     int32_t last_q = 0;
     int32_t last_steps = 0;         // refinement steps made
     double last_normest = 0.0, last_condest = 0.0;
+    int32_t last_precision = 0;     // LS_PRECISION_* of the last ls_solve
     std::vector<hipEvent_t> ev_pool; // start/end pairs, reused
     size_t ev_used = 0;             // events recorded since the last reset (even count)
     // device memory owned by the library
@@ -110,27 +111,42 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
 hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                          const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
                          double *B, int64_t ldb, double *Sb, int64_t ldsb);
+// The same sums (FP64) stored rounded once to FP32, for the mixed-precision path.
+hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                         const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
+                         float *B, int64_t ldb, float *Sb, int64_t ldsb);
 
 // ---- QR (qr.hip) ---------------------------------------------------------------------------------
-struct QrBufs {
-    double *W;           // d x ldw : [B | Sb]
+// Buffers of the blocked Householder QR in element type E (double; float on the mixed path).
+template <typename E>
+struct QrBufsT {
+    E *W;                // d x ldw : [B | Sb]
     int64_t ldw;
-    double *V;           // d x NB  : Householder vectors of the current panel
-    double *red;         // panel reduction partials
-    double *tau;         // n
-    double *Yp;          // chunk partials of V^T [V | C]
-    double *Z;           // NB x ldw
-    double *T;           // NB x NB
-    double *qtb;         // n
-    double *RT;          // n x n  (R^T, row-major)
+    E *V;                // d x NB  : Householder vectors of the current panel
+    E *red;              // panel reduction partials
+    E *tau;              // n
+    E *Yp;               // chunk partials of V^T [V | C]
+    E *Z;                // NB x ldw
+    E *T;                // NB x NB
+    E *qtb;              // n
+    E *RT;               // n x n  (R^T, row-major)
     unsigned *bar;       // grid-barrier counter of the cooperative panel kernel
 };
+using QrBufs = QrBufsT<double>;
+using QrBufs32 = QrBufsT<float>;
 void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb);
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
                               const double *Sb, const QrBufs &qb);
+hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *B, int64_t ldb,
+                              const float *Sb, const QrBufs32 &qb);
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
                      bool per_column = false);
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs32 &qb, int32_t *status,
+                     bool per_column = false);
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
+                            int32_t *status);
+hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs32 &qb, float *R, int64_t ldr,
                             int32_t *status);
 
 // ---- iteration (iterate.hip) ---------------------------------------------------------------------
@@ -152,6 +168,7 @@ hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t l
 hipError_t launch_transpose(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *RT);
 // Upper triangle of R copied with leading dimension n, zero below the diagonal.
 hipError_t launch_compact_upper(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *Rc);
+hipError_t launch_compact_upper(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *Rc);
 hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, const double *x, const IterBufs &ib, double *c,
                            double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,

@@ -10,9 +10,10 @@
 //
 // After the panel, the compact-WY form Q_p = I - V T V^T (T upper triangular) is built and the
 // trailing columns -- including the S b column, so Q is never formed -- are updated as
-// C <- C - V (T^T (V^T C)).  Both products run on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64); V^T C is split over row chunks whose partial products are summed in a
-// fixed order, so the factorization is deterministic.
+// C <- C - V (T^T (V^T C)).  Both products run on the matrix cores (v_mfma_f64_16x16x4f64, or
+// v_mfma_f32_16x16x4f32 for the single-precision factorization of the mixed-precision path);
+// V^T C is split over row chunks whose partial products are summed in a fixed order, so the
+// factorization is deterministic.  Every kernel is instantiated for FP64 and FP32.
 #include <algorithm>
 
 #include "common.hpp"
@@ -22,21 +23,43 @@ namespace {
 constexpr int kNB = 32;     // panel width
 constexpr int kRB = 256;    // rows per work-group in the panel kernels
 
-typedef double v4d __attribute__((ext_vector_type(4)));
+// 16x16x4 MFMA per element type.  Operand layout (checked on gfx950 for both): A[i][kk] from lane
+// i + 16 kk, B[kk][j] from lane j + 16 kk.  The accumulator layouts differ: element q of a lane's
+// accumulator holds D[4 q + lane/16][lane % 16] for f64 and D[4 (lane/16) + q][lane % 16] for f32.
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lane) { return 4 * q + (lane >> 4); }
+    static constexpr double kUnit = 0x1p-53;
+};
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int lane) { return 4 * (lane >> 4) + q; }
+    static constexpr float kUnit = 0x1p-24f;
+};
 
 
 // Sums v[0..kNB) across the 64 lanes of a wave by recursive halving: at each step a lane keeps half
 // of its values and adds the partner's copy of them, so 32 values need 16+8+4+2+1+1 exchanges.
 // On return lane l holds the wave total of value (l >> 1) & 31 (both lanes of a pair agree).
-__device__ __forceinline__ double wave_transpose_sum(double (&v)[kNB], int lane)
+template <typename E>
+__device__ __forceinline__ E wave_transpose_sum(E (&v)[kNB], int lane)
 {
 #pragma unroll
     for (int half = kNB / 2, off = 32; half >= 1; half >>= 1, off >>= 1) {
         const bool upper = (lane & off) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            const double send = upper ? v[i] : v[i + half];
-            const double keep = upper ? v[i + half] : v[i];
+            const E send = upper ? v[i] : v[i + half];
+            const E keep = upper ? v[i + half] : v[i];
             v[i] = keep + __shfl_xor(send, off, 64);
         }
     }
@@ -59,25 +82,26 @@ __device__ __forceinline__ int transpose_sum_index(int lane)
 //   red_in[w * kNB + l] = sum over rows of w (rows >= k) of W[i,k] W[i,p0+l]
 //   piv_in[l]           = W[k, p0+l] (the pivot row, before this step)
 // The launch writes the same quantities for column k+1 into red_out/piv_out.
+template <typename E>
 __global__ void __launch_bounds__(kRB)
-k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict__ W, int64_t ldw,
-             double *__restrict__ V, const double *__restrict__ red_in,
-             const double *__restrict__ piv_in, double *__restrict__ red_out,
-             double *__restrict__ piv_out, double *__restrict__ tau, int32_t *__restrict__ status)
+k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W, int64_t ldw,
+             E *__restrict__ V, const E *__restrict__ red_in,
+             const E *__restrict__ piv_in, E *__restrict__ red_out,
+             E *__restrict__ piv_out, E *__restrict__ tau, int32_t *__restrict__ status)
 {
-    __shared__ double s_tl[kNB];
-    __shared__ double s_f[kNB];
-    __shared__ double s_red[kRB / kNB][kNB];
-    __shared__ double s_part[kRB / 64][kNB];
-    __shared__ double s_scal[2];                  // beta, v_k
+    __shared__ E s_tl[kNB];
+    __shared__ E s_f[kNB];
+    __shared__ E s_red[kRB / kNB][kNB];
+    __shared__ E s_part[kRB / 64][kNB];
+    __shared__ E s_scal[2];                       // beta, v_k
     const int tid = threadIdx.x;
     const int64_t k = p0 + jc;
     const int64_t i = p0 + (int64_t)blockIdx.x * kRB + tid;   // this thread's row
     const bool row_ok = i < d;
 
-    double w[kNB];
+    E w[kNB];
 #pragma unroll
-    for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nbp) ? W[i * ldw + p0 + l] : 0.0;
+    for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nbp) ? W[i * ldw + p0 + l] : E(0);
 
     if (jc >= 0) {
         {   // reduce the partials: 8 contiguous groups of work-groups, then the groups in order
@@ -89,7 +113,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
             s_red[sl][l] = strided_sum<8>(red_in + (int64_t)g0 * kNB + l, cnt, kNB);
             __syncthreads();
             if (tid < kNB) {
-                double acc = 0.0;
+                E acc = E(0);
 #pragma unroll
                 for (int q = 0; q < NS; ++q) acc += s_red[q][tid];
                 s_tl[tid] = acc;
@@ -97,67 +121,67 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
         }
         __syncthreads();
         if (tid == 0) {
-            const double alpha = piv_in[jc];
-            const double ss = s_tl[jc];
-            const double sigma = sqrt(ss);
-            double beta, t;
-            if (sigma == 0.0) {               // exactly zero column: no reflection
-                beta = 0.0;
-                t = 0.0;
+            const E alpha = piv_in[jc];
+            const E ss = s_tl[jc];
+            const E sigma = sqrt(ss);
+            E beta, t;
+            if (sigma == E(0)) {               // exactly zero column: no reflection
+                beta = E(0);
+                t = E(0);
                 atomicOr(status, ST_RANK);
             } else {
-                beta = (alpha >= 0.0) ? -sigma : sigma;
-                t = 1.0 / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
+                beta = (alpha >= E(0)) ? -sigma : sigma;
+                t = E(1) / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
             }
             if (!isfinite(sigma) || !isfinite(alpha)) atomicOr(status, ST_NONFINITE);
             s_scal[0] = beta;
             s_scal[1] = alpha - beta;
             if (blockIdx.x == 0) tau[k] = t;
             for (int l = 0; l < kNB; ++l)
-                s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * piv_in[l]) : 0.0;
+                s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * piv_in[l]) : E(0);
         }
         __syncthreads();
         if (row_ok) {
-            double *vrow = V + (i - p0) * kNB;
+            E *vrow = V + (i - p0) * kNB;
             if (i >= k) {
-                double wjc = 0.0;
+                E wjc = E(0);
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
                     if (l == jc) wjc = w[l];
-                const double vi = (i == k) ? s_scal[1] : wjc;
+                const E vi = (i == k) ? s_scal[1] : wjc;
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
                     if (l > jc && l < nbp) w[l] -= s_f[l] * vi;
                 vrow[jc] = vi;
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
-                    if (l == jc) w[l] = (i == k) ? s_scal[0] : 0.0;
+                    if (l == jc) w[l] = (i == k) ? s_scal[0] : E(0);
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
                     if (l >= jc && l < nbp) W[i * ldw + p0 + l] = w[l];
             } else {
-                vrow[jc] = 0.0;
+                vrow[jc] = E(0);
             }
         }
     } else if (row_ok) {
-        double *vrow = V + (i - p0) * kNB;
+        E *vrow = V + (i - p0) * kNB;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) vrow[l] = 0.0;
+        for (int l = 0; l < kNB; ++l) vrow[l] = E(0);
     }
 
     // Partial sums for column k+1 over rows >= k+1, and its pivot row.
     const int jn = jc + 1;
     if (jn < nbp) {
         const bool part = row_ok && i >= k + 1;
-        double wn = 0.0;
+        E wn = E(0);
 #pragma unroll
         for (int l = 0; l < kNB; ++l)
             if (l == jn && part) wn = w[l];
         const int wave = tid >> 6, lane = tid & 63;
-        double pv[kNB];
+        E pv[kNB];
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) pv[l] = (l >= jn && l < nbp) ? wn * w[l] : 0.0;
-        const double tot = wave_transpose_sum(pv, lane);
+        for (int l = 0; l < kNB; ++l) pv[l] = (l >= jn && l < nbp) ? wn * w[l] : E(0);
+        const E tot = wave_transpose_sum(pv, lane);
         if ((lane & 1) == 0) s_part[wave][transpose_sum_index(lane)] = tot;
         if (i == k + 1) {
 #pragma unroll
@@ -165,7 +189,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, double *__restrict
         }
         __syncthreads();
         if (tid < kNB) {
-            double acc = 0.0;
+            E acc = E(0);
 #pragma unroll
             for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
             red_out[blockIdx.x * kNB + tid] = acc;
@@ -207,48 +231,48 @@ __device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned 
     __syncthreads();
 }
 
-template <int RPT>
+template <typename E, int RPT>
 __global__ void __launch_bounds__(kRB)
-k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, int64_t ldw,
-             double *__restrict__ V, double *__restrict__ red, double *__restrict__ tau,
+k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t ldw,
+             E *__restrict__ V, E *__restrict__ red, E *__restrict__ tau,
              unsigned *__restrict__ bar, int32_t *__restrict__ status)
 {
-    __shared__ double s_tl[kNB];
-    __shared__ double s_f[kNB];
-    __shared__ double s_part[kRB / 64][kNB];
-    __shared__ double s_red[kRB / kNB][kNB];
-    __shared__ double s_scal[2];
-    __shared__ double s_piv[kNB];
+    __shared__ E s_tl[kNB];
+    __shared__ E s_f[kNB];
+    __shared__ E s_part[kRB / 64][kNB];
+    __shared__ E s_red[kRB / kNB][kNB];
+    __shared__ E s_scal[2];
+    __shared__ E s_piv[kNB];
     __shared__ int s_haspiv;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    double *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
+    E *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
     const int tidx = transpose_sum_index(lane);
     int64_t row[RPT];
     bool ok[RPT];
-    double w[RPT][kNB];
-    double vv[RPT][kNB];                                    // Householder vectors, row by row
+    E w[RPT][kNB];
+    E vv[RPT][kNB];                                    // Householder vectors, row by row
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * kRB + tid;
         ok[r] = row[r] < d;
 #pragma unroll
         for (int l = 0; l < kNB; ++l) {
-            w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : 0.0;
-            vv[r][l] = 0.0;
+            w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : E(0);
+            vv[r][l] = E(0);
         }
     }
     for (int jc = 0; jc < nbp; ++jc) {
         const int64_t k = p0 + jc;
         const int pb = jc & 1;
-        double *rb = red + (int64_t)pb * nwg * kNB;
+        E *rb = red + (int64_t)pb * nwg * kNB;
         // (1) partial sums of column jc over my rows >= k, and the pivot row
         {
-            double pv[kNB];
+            E pv[kNB];
 #pragma unroll
-            for (int l = 0; l < kNB; ++l) pv[l] = 0.0;
+            for (int l = 0; l < kNB; ++l) pv[l] = E(0);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                double wj = 0.0;
+                E wj = E(0);
 #pragma unroll
                 for (int q = 0; q < kNB; ++q)
                     if (q == jc) wj = w[r][q];
@@ -257,7 +281,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
                 for (int l = 0; l < kNB; ++l)
                     if (use && l >= jc && l < nbp) pv[l] += wj * w[r][l];
             }
-            const double tot = wave_transpose_sum(pv, lane);
+            const E tot = wave_transpose_sum(pv, lane);
             if ((lane & 1) == 0) s_part[wave][tidx] = tot;
         }
         if (tid == 0) s_haspiv = 0;
@@ -273,7 +297,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
         // wave 0 publishes the partials (and the pivot row, from its owner): the barrier's release
         // fence, issued by thread 0, then covers every store the other work-groups will read
         if (tid < kNB) {
-            double acc = 0.0;
+            E acc = E(0);
 #pragma unroll
             for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
             rb[(int64_t)blockIdx.x * kNB + tid] = acc;
@@ -291,7 +315,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
             if (tid < kNB) s_piv[tid] = piv[pb * kNB + tid];
             __syncthreads();
             if (tid < kNB) {
-                double acc = 0.0;
+                E acc = E(0);
 #pragma unroll
                 for (int q = 0; q < NS; ++q) acc += s_red[q][tid];
                 s_tl[tid] = acc;
@@ -301,20 +325,20 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
         // (3) reflector H = I - tau v v^T, beta = -sign(alpha) sigma (every one of the first kNB
         // threads forms the same scalars), then the update coefficients of the panel columns
         if (tid < kNB) {
-            const double alpha = s_piv[jc];
-            const double sigma = sqrt(s_tl[jc]);
-            double beta, t;
-            if (sigma == 0.0) {
-                beta = 0.0;
-                t = 0.0;
+            const E alpha = s_piv[jc];
+            const E sigma = sqrt(s_tl[jc]);
+            E beta, t;
+            if (sigma == E(0)) {
+                beta = E(0);
+                t = E(0);
             } else {
-                beta = (alpha >= 0.0) ? -sigma : sigma;
-                t = 1.0 / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
+                beta = (alpha >= E(0)) ? -sigma : sigma;
+                t = E(1) / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
             }
             const int l = tid;
-            s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * s_piv[l]) : 0.0;
+            s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * s_piv[l]) : E(0);
             if (tid == 0) {
-                if (sigma == 0.0) atomicOr(status, ST_RANK);
+                if (sigma == E(0)) atomicOr(status, ST_RANK);
                 if (!isfinite(sigma) || !isfinite(alpha)) atomicOr(status, ST_NONFINITE);
                 s_scal[0] = beta;
                 s_scal[1] = alpha - beta;
@@ -325,11 +349,11 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (!ok[r] || row[r] < k) continue;
-            double wjc = 0.0;
+            E wjc = E(0);
 #pragma unroll
             for (int q = 0; q < kNB; ++q)
                 if (q == jc) wjc = w[r][q];
-            const double vi = (row[r] == k) ? s_scal[1] : wjc;
+            const E vi = (row[r] == k) ? s_scal[1] : wjc;
 #pragma unroll
             for (int l = 0; l < kNB; ++l)
                 if (l > jc && l < nbp) w[r][l] -= s_f[l] * vi;
@@ -337,14 +361,14 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, double *__restrict__ W, in
             for (int l = 0; l < kNB; ++l)
                 if (l == jc) {
                     vv[r][l] = vi;
-                    w[r][l] = (row[r] == k) ? s_scal[0] : 0.0;
+                    w[r][l] = (row[r] == k) ? s_scal[0] : E(0);
                 }
         }
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         if (!ok[r]) continue;
-        double *vrow = V + (row[r] - p0) * kNB;
+        E *vrow = V + (row[r] - p0) * kNB;
 #pragma unroll
         for (int l = 0; l < kNB; ++l) {
             if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
@@ -361,12 +385,12 @@ __global__ void k_zero_u32(unsigned *p, int n)
 
 // out[ch][a][c] = sum over rows r of chunk ch of V[r][a] X[r][c]  (a < kNB, c < ncx).
 // Work-group tile: kNB x 64 columns; wave w computes columns 16w..16w+15 for both 16-row halves.
-// MFMA 16x16x4 f64 operand layout (checked on gfx950): A[i][kk] from lane i + 16 kk, B[kk][j] from
-// lane j + 16 kk; element q of a lane's accumulator holds D[4 q + lane/16][lane % 16].
+// Operands and accumulator rows as in Mfma<E>.
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
-              const double *__restrict__ X, int64_t ldx, int64_t ncx, int64_t ldo,
-              double *__restrict__ out)
+k_vtx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V,
+              const E *__restrict__ X, int64_t ldx, int64_t ncx, int64_t ldo,
+              E *__restrict__ out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t ch = blockIdx.x;
@@ -375,21 +399,21 @@ k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
     const int64_t col = (int64_t)blockIdx.y * 64 + 16 * wave + (lane & 15);
     const bool col_ok = col < ncx;
     const int kk = lane >> 4, ii = lane & 15;
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    typename Mfma<E>::v4 acc0 = {E(0), E(0), E(0), E(0)}, acc1 = {E(0), E(0), E(0), E(0)};
     for (int64_t r = r_lo; r < r_hi; r += 4) {
         const int64_t rr = r + kk;
         const bool ok = rr < r_hi;
-        const double a0 = ok ? V[rr * kNB + ii] : 0.0;
-        const double a1 = ok ? V[rr * kNB + 16 + ii] : 0.0;
-        const double bb = (ok && col_ok) ? X[rr * ldx + col] : 0.0;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, acc1, 0, 0, 0);
+        const E a0 = ok ? V[rr * kNB + ii] : E(0);
+        const E a1 = ok ? V[rr * kNB + 16 + ii] : E(0);
+        const E bb = (ok && col_ok) ? X[rr * ldx + col] : E(0);
+        acc0 = Mfma<E>::mma(a0, bb, acc0);
+        acc1 = Mfma<E>::mma(a1, bb, acc1);
     }
     if (col_ok) {
-        double *o = out + ch * (int64_t)kNB * ldo + col;
+        E *o = out + ch * (int64_t)kNB * ldo + col;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int a = 4 * q + (lane >> 4);
+            const int a = Mfma<E>::row(q, lane);
             o[(int64_t)a * ldo] = acc0[q];
             o[(int64_t)(16 + a) * ldo] = acc1[q];
         }
@@ -397,23 +421,24 @@ k_vtx_partial(int64_t rows, int64_t chunk, const double *__restrict__ V,
 }
 
 // T of the compact-WY form: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_form_t(int nch, int64_t ldo, const double *__restrict__ Gp, const double *__restrict__ tau,
-         int64_t p0, int nbp, double *__restrict__ T)
+k_form_t(int nch, int64_t ldo, const E *__restrict__ Gp, const E *__restrict__ tau,
+         int64_t p0, int nbp, E *__restrict__ T)
 {
-    __shared__ double G[kNB][kNB + 1];
-    __shared__ double Ts[kNB][kNB + 1];
+    __shared__ E G[kNB][kNB + 1];
+    __shared__ E Ts[kNB][kNB + 1];
     const int tid = threadIdx.x;
     for (int e = tid; e < kNB * kNB; e += blockDim.x) {
         const int a = e / kNB, c = e % kNB;
         G[a][c] = strided_sum<8>(Gp + (int64_t)a * ldo + c, nch, (int64_t)kNB * ldo);
-        Ts[a][c] = 0.0;
+        Ts[a][c] = E(0);
     }
     __syncthreads();
     for (int j = 0; j < nbp; ++j) {
-        const double tj = tau[p0 + j];
+        const E tj = tau[p0 + j];
         if (tid < j) {
-            double acc = 0.0;
+            E acc = E(0);
             for (int q = tid; q < j; ++q) acc += Ts[tid][q] * G[q][j];
             Ts[tid][j] = -tj * acc;
         }
@@ -428,24 +453,25 @@ k_form_t(int nch, int64_t ldo, const double *__restrict__ Gp, const double *__re
 constexpr int kApplyCols = 32;
 constexpr int kApplySlices = 4;
 
+template <typename E>
 __global__ void __launch_bounds__(kApplyCols * kApplySlices)
-k_apply_t(int nch, int64_t ldo, const double *__restrict__ Yp, const double *__restrict__ T,
-          int64_t nc, double *__restrict__ Z, int64_t ldz)
+k_apply_t(int nch, int64_t ldo, const E *__restrict__ Yp, const E *__restrict__ T,
+          int64_t nc, E *__restrict__ Z, int64_t ldz)
 {
-    __shared__ double Ts[kNB * kNB];
-    __shared__ double ys[kApplySlices][kNB][kApplyCols + 1];
+    __shared__ E Ts[kNB * kNB];
+    __shared__ E ys[kApplySlices][kNB][kApplyCols + 1];
     for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) Ts[e] = T[e];
     const int cl = threadIdx.x % kApplyCols, sl = threadIdx.x / kApplyCols;
     const int64_t c = (int64_t)blockIdx.x * kApplyCols + cl;
     const int per = (nch + kApplySlices - 1) / kApplySlices;
     const int g0 = sl * per;
     const int cnt = (g0 + per < nch) ? per : (nch > g0 ? nch - g0 : 0);
-    double y[kNB];
+    E y[kNB];
 #pragma unroll
-    for (int a = 0; a < kNB; ++a) y[a] = 0.0;
+    for (int a = 0; a < kNB; ++a) y[a] = E(0);
     if (c < nc) {
         for (int g = g0; g < g0 + cnt; ++g) {
-            const double *p = Yp + (int64_t)g * kNB * ldo + c;
+            const E *p = Yp + (int64_t)g * kNB * ldo + c;
 #pragma unroll
             for (int a = 0; a < kNB; ++a) y[a] += p[(int64_t)a * ldo];
         }
@@ -456,14 +482,14 @@ k_apply_t(int nch, int64_t ldo, const double *__restrict__ Yp, const double *__r
     if (sl != 0 || c >= nc) return;
 #pragma unroll
     for (int a = 0; a < kNB; ++a) {
-        double t = 0.0;
+        E t = E(0);
 #pragma unroll
         for (int q = 0; q < kApplySlices; ++q) t += ys[q][a][cl];
         y[a] = t;
     }
 #pragma unroll
     for (int a = 0; a < kNB; ++a) {
-        double z = 0.0;
+        E z = E(0);
 #pragma unroll
         for (int b2 = 0; b2 <= a; ++b2) z += Ts[b2 * kNB + a] * y[b2];
         Z[(int64_t)a * ldz + c] = z;
@@ -472,9 +498,10 @@ k_apply_t(int nch, int64_t ldo, const double *__restrict__ Yp, const double *__r
 
 // C[r][c] -= sum_a V[r][a] Z[a][c] over rows r < rows, columns c < nc.
 // Work-group tile 64 x 64: wave w owns rows 16w..16w+15 and four 16-column MFMA blocks.
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_update_c(int64_t rows, int64_t nc, const double *__restrict__ V, const double *__restrict__ Z,
-           int64_t ldz, double *__restrict__ C, int64_t ldc)
+k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restrict__ Z,
+           int64_t ldz, E *__restrict__ C, int64_t ldc)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * wave;
@@ -482,17 +509,17 @@ k_update_c(int64_t rows, int64_t nc, const double *__restrict__ V, const double 
     const int kk = lane >> 4, ii = lane & 15;
     const int64_t ra = r0 + ii;
     const bool ra_ok = ra < rows;
-    v4d acc[4];
+    typename Mfma<E>::v4 acc[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
 #pragma unroll
     for (int a = 0; a < kNB; a += 4) {
-        const double av = ra_ok ? V[ra * kNB + a + kk] : 0.0;
+        const E av = ra_ok ? V[ra * kNB + a + kk] : E(0);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int64_t cc = c0 + 16 * cb + ii;
-            const double bv = (cc < nc) ? Z[(int64_t)(a + kk) * ldz + cc] : 0.0;
-            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+            const E bv = (cc < nc) ? Z[(int64_t)(a + kk) * ldz + cc] : E(0);
+            acc[cb] = Mfma<E>::mma(av, bv, acc[cb]);
         }
     }
 #pragma unroll
@@ -501,15 +528,16 @@ k_update_c(int64_t rows, int64_t nc, const double *__restrict__ V, const double 
         if (cc >= nc) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t r = r0 + 4 * q + kk;
+            const int64_t r = r0 + Mfma<E>::row(q, lane);
             if (r < rows) C[r * ldc + cc] -= acc[cb][q];
         }
     }
 }
 
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_copy_sketch(int64_t d, int64_t n, const double *__restrict__ B, int64_t ldb,
-              const double *__restrict__ Sb, double *__restrict__ W, int64_t ldw)
+k_copy_sketch(int64_t d, int64_t n, const E *__restrict__ B, int64_t ldb,
+              const E *__restrict__ Sb, E *__restrict__ W, int64_t ldw)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w = n + 1;
@@ -519,19 +547,20 @@ k_copy_sketch(int64_t d, int64_t n, const double *__restrict__ B, int64_t ldb,
 }
 
 // R (upper triangle of W), R^T, Q^T Sb; flags NaN/Inf.
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_extract_r(int64_t n, const double *__restrict__ W, int64_t ldw, double *__restrict__ R,
-            int64_t ldr, double *__restrict__ RT, double *__restrict__ qtb,
+k_extract_r(int64_t n, const E *__restrict__ W, int64_t ldw, E *__restrict__ R,
+            int64_t ldr, E *__restrict__ RT, E *__restrict__ qtb,
             int32_t *__restrict__ status)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     const int64_t i = e / n, c = e % n;
-    const double v = (c >= i) ? W[i * ldw + c] : 0.0;
+    const E v = (c >= i) ? W[i * ldw + c] : E(0);
     if (R) R[i * ldr + c] = v;
     RT[c * n + i] = v;
     if (c == 0) {
-        const double q = W[i * ldw + n];
+        const E q = W[i * ldw + n];
         qtb[i] = q;
         if (!isfinite(q)) atomicOr(status, ST_NONFINITE);
     }
@@ -539,18 +568,19 @@ k_extract_r(int64_t n, const double *__restrict__ W, int64_t ldw, double *__rest
 }
 
 // Rank test on diag(R): |R_kk| <= n u max_j |R_jj|.
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_rank_check(int64_t n, const double *__restrict__ RT, int32_t *__restrict__ status)
+k_rank_check(int64_t n, const E *__restrict__ RT, int32_t *__restrict__ status)
 {
-    __shared__ double smax[4];
-    double mx = 0.0;
+    __shared__ E smax[4];
+    E mx = E(0);
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) mx = fmax(mx, fabs(RT[k * n + k]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = mx;
     __syncthreads();
     mx = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
-    const double tol = (double)n * 0x1p-53 * mx;
+    const E tol = (E)n * Mfma<E>::kUnit * mx;
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
         if (!(fabs(RT[k * n + k]) > tol)) atomicOr(status, ST_RANK);
 }
@@ -568,38 +598,55 @@ int64_t chunk_rows(int64_t rows)
 
 }  // namespace
 
-void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb)
+template <typename E>
+static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb)
 {
     qb.ldw = ceil_div(n + 1, 8) * 8;
-    qb.W = ar.take<double>((size_t)d * (size_t)qb.ldw);
-    qb.V = ar.take<double>((size_t)d * kNB);
-    qb.red = ar.take<double>((size_t)2 * (size_t)(panel_wgs_max(d) * kNB + kNB));
-    qb.tau = ar.take<double>((size_t)n);
+    qb.W = ar.take<E>((size_t)d * (size_t)qb.ldw);
+    qb.V = ar.take<E>((size_t)d * kNB);
+    qb.red = ar.take<E>((size_t)2 * (size_t)(panel_wgs_max(d) * kNB + kNB));
+    qb.tau = ar.take<E>((size_t)n);
     // every panel uses at most min(64, ceil(rows/256)) chunks (see chunk_rows)
     const int64_t nch = std::min<int64_t>(64, ceil_div(d, 256));
     const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
-    qb.Yp = ar.take<double>((size_t)nch * kNB * (size_t)ldo);
-    qb.Z = ar.take<double>((size_t)kNB * (size_t)qb.ldw);
-    qb.T = ar.take<double>((size_t)kNB * kNB);
-    qb.qtb = ar.take<double>((size_t)n);
-    qb.RT = ar.take<double>((size_t)n * (size_t)n);
+    qb.Yp = ar.take<E>((size_t)nch * kNB * (size_t)ldo);
+    qb.Z = ar.take<E>((size_t)kNB * (size_t)qb.ldw);
+    qb.T = ar.take<E>((size_t)kNB * kNB);
+    qb.qtb = ar.take<E>((size_t)n);
+    qb.RT = ar.take<E>((size_t)n * (size_t)n);
     qb.bar = ar.take<unsigned>(1024);
+}
+
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb) { qr_bufs_impl(ar, d, n, qb); }
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb) { qr_bufs_impl(ar, d, n, qb); }
+
+template <typename E>
+static hipError_t copy_sketch_impl(hipStream_t s, int64_t d, int64_t n, const E *B, int64_t ldb,
+                                   const E *Sb, const QrBufsT<E> &qb)
+{
+    const int64_t total = d * (n + 1);
+    hipLaunchKernelGGL(k_copy_sketch<E>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, d, n,
+                       B, ldb, Sb, qb.W, qb.ldw);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
                               const double *Sb, const QrBufs &qb)
 {
-    const int64_t total = d * (n + 1);
-    hipLaunchKernelGGL(k_copy_sketch, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, d, n,
-                       B, ldb, Sb, qb.W, qb.ldw);
-    return hipGetLastError();
+    return copy_sketch_impl(s, d, n, B, ldb, Sb, qb);
+}
+
+hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *B, int64_t ldb,
+                              const float *Sb, const QrBufs32 &qb)
+{
+    return copy_sketch_impl(s, d, n, B, ldb, Sb, qb);
 }
 
 namespace {
 
-// Work-groups of k_panel_coop<RPT> that can be co-resident on the current device (0: cooperative
+// Work-groups of k_panel_coop<E, RPT> that can be co-resident on the current device (0: cooperative
 // launch unavailable).  Cached per device.
-template <int RPT>
+template <typename E, int RPT>
 int coop_capacity()
 {
     static int cache[64];
@@ -609,7 +656,7 @@ int coop_capacity()
     int coop = 0, cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<RPT>), kRB, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<E, RPT>), kRB, 0) != hipSuccess ||
         per_cu <= 0) {
         (void)hipGetLastError();
         cache[dev] = -1;
@@ -619,57 +666,56 @@ int coop_capacity()
     return cache[dev];
 }
 
-template <int RPT>
-hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, double *W,
-                             int64_t ldw, double *V, double *red, double *tau, unsigned *bar,
-                             int32_t *status)
+template <typename E, int RPT>
+hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, E *W,
+                             int64_t ldw, E *V, E *red, E *tau, unsigned *bar, int32_t *status)
 {
     hipLaunchKernelGGL(k_zero_u32, dim3((nwg + 255) / 256), dim3(256), 0, s, bar, nwg);
     void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &status};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<RPT>), dim3(nwg),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT>), dim3(nwg),
                                       dim3(kRB), args, 0, s);
 }
 
 // One panel by the cooperative kernel if the device can hold its grid; returns false to request
 // the per-column path.
-bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufs &qb,
+template <typename E>
+bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb,
                        int32_t *status, hipError_t &err)
 {
     const int64_t rows = d - p0;
     err = hipSuccess;
     int nwg = (int)ceil_div(rows, kRB);
-    if (nwg <= coop_capacity<1>()) {
-        err = launch_panel_coop<1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
+    if (nwg <= coop_capacity<E, 1>()) {
+        err = launch_panel_coop<E, 1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
         return true;
     }
     nwg = (int)ceil_div(rows, 2 * kRB);
-    if (nwg <= coop_capacity<2>()) {
-        err = launch_panel_coop<2>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
+    if (nwg <= coop_capacity<E, 2>()) {
+        err = launch_panel_coop<E, 2>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
         return true;
     }
     return false;
 }
 
-}  // namespace
-
-hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
-                     bool per_column)
+template <typename E>
+hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, int32_t *status,
+                   bool per_column)
 {
     const int64_t ldw = qb.ldw;
     const int64_t red_stride = panel_wgs_max(d) * kNB + kNB;
-    double *redA = qb.red, *redB = qb.red + red_stride;
+    E *redA = qb.red, *redB = qb.red + red_stride;
     for (int64_t p0 = 0; p0 < n; p0 += kNB) {
         const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
         const int64_t rows = d - p0;
         hipError_t err = hipSuccess;
         if (per_column || !panel_cooperative(s, d, p0, nbp, qb, status, err)) {
             const int nwg = (int)ceil_div(rows, kRB);
-            double *rin = redA, *rout = redB;
+            E *rin = redA, *rout = redB;
             for (int jc = -1; jc < nbp; ++jc) {
-                hipLaunchKernelGGL(k_panel_step, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
+                hipLaunchKernelGGL(k_panel_step<E>, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
                                    ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
                                    rout + (int64_t)nwg * kNB, qb.tau, status);
-                double *t = rin;
+                E *t = rin;
                 rin = rout;
                 rout = t;
             }
@@ -680,25 +726,52 @@ hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int3
         const int64_t chunk = chunk_rows(rows);
         const int nch = (int)ceil_div(rows, chunk);
         const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
-        hipLaunchKernelGGL(k_vtx_partial, dim3(nch, 1), dim3(256), 0, s, rows, chunk, qb.V,
-                           (const double *)qb.V, (int64_t)kNB, (int64_t)kNB, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_form_t, dim3(1), dim3(256), 0, s, nch, ldo, qb.Yp, qb.tau, p0, nbp, qb.T);
-        const double *C0 = qb.W + p0 * ldw + c_first;
-        hipLaunchKernelGGL(k_vtx_partial, dim3(nch, (unsigned)ceil_div(nc, 64)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_vtx_partial<E>, dim3(nch, 1), dim3(256), 0, s, rows, chunk, qb.V,
+                           (const E *)qb.V, (int64_t)kNB, (int64_t)kNB, ldo, qb.Yp);
+        hipLaunchKernelGGL(k_form_t<E>, dim3(1), dim3(256), 0, s, nch, ldo, qb.Yp, qb.tau, p0, nbp, qb.T);
+        const E *C0 = qb.W + p0 * ldw + c_first;
+        hipLaunchKernelGGL(k_vtx_partial<E>, dim3(nch, (unsigned)ceil_div(nc, 64)), dim3(256), 0, s,
                            rows, chunk, qb.V, C0, ldw, nc, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_apply_t, dim3((unsigned)ceil_div(nc, kApplyCols)), dim3(kApplyCols * kApplySlices), 0, s, nch, ldo,
+        hipLaunchKernelGGL(k_apply_t<E>, dim3((unsigned)ceil_div(nc, kApplyCols)), dim3(kApplyCols * kApplySlices), 0, s, nch, ldo,
                            qb.Yp, qb.T, nc, qb.Z, ldw);
-        hipLaunchKernelGGL(k_update_c, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
+        hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
                            dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);
     }
     return hipGetLastError();
 }
 
+template <typename E>
+hipError_t extract_r_impl(hipStream_t s, int64_t n, const QrBufsT<E> &qb, E *R, int64_t ldr,
+                          int32_t *status)
+{
+    hipLaunchKernelGGL(k_extract_r<E>, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, qb.W,
+                       qb.ldw, R, ldr, qb.RT, qb.qtb, status);
+    hipLaunchKernelGGL(k_rank_check<E>, dim3(1), dim3(256), 0, s, n, qb.RT, status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
+                     bool per_column)
+{
+    return qr_impl(s, d, n, qb, status, per_column);
+}
+
+hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs32 &qb, int32_t *status,
+                     bool per_column)
+{
+    return qr_impl(s, d, n, qb, status, per_column);
+}
+
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
                             int32_t *status)
 {
-    hipLaunchKernelGGL(k_extract_r, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, qb.W,
-                       qb.ldw, R, ldr, qb.RT, qb.qtb, status);
-    hipLaunchKernelGGL(k_rank_check, dim3(1), dim3(256), 0, s, n, qb.RT, status);
-    return hipGetLastError();
+    return extract_r_impl(s, n, qb, R, ldr, status);
+}
+
+hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs32 &qb, float *R, int64_t ldr,
+                            int32_t *status)
+{
+    return extract_r_impl(s, n, qb, R, ldr, status);
 }

@@ -172,12 +172,13 @@ k_csr_sort(int64_t d, const int32_t *__restrict__ rowptr, uint32_t *__restrict__
 // One wave per (sketch row k, column tile).  Lane l owns columns c0 + l + 64 c, c < CPL, so every
 // load instruction reads 64 consecutive doubles of a row of A.  Terms are added in ascending j;
 // four rows are loaded before they are added so that several rows are in flight per wave.
-template <int CPL>
+// The sums are FP64; OT is the stored type (float on the mixed path: each entry rounded once).
+template <int CPL, typename OT>
 __global__ void __launch_bounds__(64)
 k_gather(int64_t n, int32_t ntiles, const double *__restrict__ A, int64_t lda,
          const double *__restrict__ b, const int32_t *__restrict__ rowptr,
-         const uint32_t *__restrict__ cols, double scale, double *__restrict__ B, int64_t ldb,
-         double *__restrict__ Sb, int64_t ldsb)
+         const uint32_t *__restrict__ cols, double scale, OT *__restrict__ B, int64_t ldb,
+         OT *__restrict__ Sb, int64_t ldsb)
 {
     const int64_t k = blockIdx.x / ntiles;
     const int tile = blockIdx.x % ntiles;
@@ -229,11 +230,11 @@ k_gather(int64_t n, int32_t ntiles, const double *__restrict__ A, int64_t lda,
             sb = neg ? sb - bj : sb + bj;
         }
     }
-    double *out = B + k * ldb + c0;
+    OT *out = B + k * ldb + c0;
 #pragma unroll
     for (int c = 0; c < CPL; ++c)
-        if (ok[c]) out[64 * c] = acc[c] * scale;
-    if (do_b) Sb[k * ldsb] = sb * scale;
+        if (ok[c]) out[64 * c] = (OT)(acc[c] * scale);
+    if (do_b) Sb[k * ldsb] = (OT)(sb * scale);
 }
 
 inline unsigned blocks_for(int64_t count, int per) { return (unsigned)((count + per - 1) / per); }
@@ -278,9 +279,12 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
     return hipGetLastError();
 }
 
-hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
-                         const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                         double *B, int64_t ldb, double *Sb, int64_t ldsb)
+namespace {
+
+template <typename OT>
+hipError_t gather_impl(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                       const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
+                       OT *B, int64_t ldb, OT *Sb, int64_t ldsb)
 {
     // Columns per lane: the smallest of 1, 2, 4, 8 covering n in one tile, else tiles of 512.
     int cpl = 8;
@@ -290,10 +294,26 @@ hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, i
     const int32_t ntiles = (int32_t)((n + 64 * cpl - 1) / (64 * cpl));
     const dim3 grid((unsigned)(d * ntiles));
     switch (cpl) {
-    case 1: hipLaunchKernelGGL(k_gather<1>, grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
-    case 2: hipLaunchKernelGGL(k_gather<2>, grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
-    case 4: hipLaunchKernelGGL(k_gather<4>, grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
-    default: hipLaunchKernelGGL(k_gather<8>, grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
+    case 1: hipLaunchKernelGGL((k_gather<1, OT>), grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
+    case 2: hipLaunchKernelGGL((k_gather<2, OT>), grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, OT>), grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
+    default: hipLaunchKernelGGL((k_gather<8, OT>), grid, dim3(64), 0, s, n, ntiles, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb); break;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                         const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
+                         double *B, int64_t ldb, double *Sb, int64_t ldsb)
+{
+    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb);
+}
+
+hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                         const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
+                         float *B, int64_t ldb, float *Sb, int64_t ldsb)
+{
+    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb);
 }

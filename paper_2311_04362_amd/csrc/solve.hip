@@ -740,13 +740,14 @@ k_transpose(int64_t n, const T *__restrict__ R, int64_t ldr, T *__restrict__ RT)
 }
 
 // Rc = upper triangle of R with leading dimension n (zero below the diagonal).
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_compact_upper(int64_t n, const double *__restrict__ R, int64_t ldr, double *__restrict__ Rc)
+k_compact_upper(int64_t n, const T *__restrict__ R, int64_t ldr, T *__restrict__ Rc)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     const int64_t i = e / n, j = e % n;
-    Rc[e] = (j >= i) ? R[i * ldr + j] : 0.0;
+    Rc[e] = (j >= i) ? R[i * ldr + j] : T(0);
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -797,7 +798,13 @@ hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t l
 
 hipError_t launch_compact_upper(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *Rc)
 {
-    hipLaunchKernelGGL(k_compact_upper, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, R, ldr, Rc);
+    hipLaunchKernelGGL(k_compact_upper<double>, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, R, ldr, Rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_upper(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *Rc)
+{
+    hipLaunchKernelGGL(k_compact_upper<float>, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, s, n, R, ldr, Rc);
     return hipGetLastError();
 }
 

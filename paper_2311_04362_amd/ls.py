@@ -21,11 +21,12 @@ STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_
 OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL, \
     OPT_STOP, OPT_GAMMA, OPT_RHO = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 NORMEST_SEED_OFFSET = 0x632BE59BD9B4E019
+PRECISION_FP64, PRECISION_MIXED, PRECISION_FELL_BACK_COND, PRECISION_FELL_BACK_GROWTH = 0, 1, 2, 3
 
 EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_option",
            "ls_get_option", "ls_sketch_embedding", "ls_sketch_csr", "ls_sketch", "ls_qr_sketch",
            "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile",
-           "ls_solve_info"]
+           "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -68,7 +69,10 @@ def load():
         "ls_sync": ([_vp, _vp], ctypes.c_int),
         "ls_profile": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64), _i32], ctypes.c_int),
         "ls_solve_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64),
-                           ctypes.POINTER(_f64)], ctypes.c_int),
+                           ctypes.POINTER(_f64), ctypes.POINTER(_i32)], ctypes.c_int),
+        "ls_sketch_f32": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _u64, _vp, _i64, _vp], ctypes.c_int),
+        "ls_qr_sketch_f32": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp], ctypes.c_int),
+        "ls_precond_solve_f32": ([_vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -212,11 +216,37 @@ class Context:
         self._check(self._L.ls_sync(self.h, self._stream()), "ls_sync")
 
     def solve_info(self):
-        """(d used, refinement steps made, normest, condest) of the last solve."""
-        d, q, ne, ce = _i64(), _i32(), _f64(), _f64()
+        """(d used, refinement steps made, normest, condest, precision used) of the last solve."""
+        d, q, ne, ce, pr = _i64(), _i32(), _f64(), _f64(), _i32()
         self._check(self._L.ls_solve_info(self.h, ctypes.byref(d), ctypes.byref(q), ctypes.byref(ne),
-                                          ctypes.byref(ce)), "ls_solve_info")
-        return d.value, q.value, ne.value, ce.value
+                                          ctypes.byref(ce), ctypes.byref(pr)), "ls_solve_info")
+        return d.value, q.value, ne.value, ce.value, pr.value
+
+    # mixed-precision pieces (FP32 sketch, QR and R-solves)
+    def sketch_f32(self, A: torch.Tensor, b, d: int, zeta: int, seed: int):
+        m, n, lda = _mat(A, "A")
+        B = torch.empty((d, n), dtype=torch.float32, device=A.device)
+        Sb = torch.empty(d, dtype=torch.float32, device=A.device) if b is not None else None
+        self._check(self._L.ls_sketch_f32(self.h, self._stream(), m, n, _ptr(A), lda,
+                                          _ptr(None if b is None else _vec(b, "b")), d, zeta, seed,
+                                          _ptr(B), n, _ptr(Sb)), "ls_sketch_f32")
+        return B, Sb
+
+    def qr_sketch_f32(self, B: torch.Tensor, Sb: torch.Tensor, want_x0: bool = True):
+        d, n, ldb = _mat(B, "B", torch.float32)
+        R = torch.empty((n, n), dtype=torch.float32, device=B.device)
+        x0 = torch.empty(n, dtype=torch.float64, device=B.device) if want_x0 else None
+        self._check(self._L.ls_qr_sketch_f32(self.h, self._stream(), d, n, _ptr(B), ldb,
+                                             _ptr(_vec(Sb, "Sb", torch.float32)), _ptr(R), n, _ptr(x0)),
+                    "ls_qr_sketch_f32")
+        return R, x0
+
+    def precond_solve_f32(self, R: torch.Tensor, c: torch.Tensor):
+        n, _, ldr = _mat(R, "R", torch.float32)
+        d = torch.empty(n, dtype=torch.float64, device=R.device)
+        self._check(self._L.ls_precond_solve_f32(self.h, self._stream(), n, _ptr(R), ldr,
+                                                 _ptr(_vec(c, "c")), _ptr(d)), "ls_precond_solve_f32")
+        return d
 
     def profile(self, reset: bool = True):
         """(summed fused-pass kernel ms, launches) since the last reset (needs OPT_PROFILE = 1)."""

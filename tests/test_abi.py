@@ -152,6 +152,25 @@ def test_iterate_damping_needs_parameters(L, hctx):
     assert L.ls_iterate(hctx, S0, 100, 10, P, 10, P, P, 10, P, 3, NUL) == ls.LS_ERR_DEVICE
 
 
+def test_precision_option_and_f32_argument_errors(L, hctx):
+    iv, dv = ctypes.c_int64(), ctypes.c_double()
+    assert L.ls_set_option(hctx, ls.OPT_PRECISION, 1, 0.0) == ls.LS_OK
+    L.ls_get_option(hctx, ls.OPT_PRECISION, ctypes.byref(iv), ctypes.byref(dv))
+    assert iv.value == 1
+    assert L.ls_set_option(hctx, ls.OPT_PRECISION, 2, 0.0) == ls.LS_ERR_ARG
+    P4 = ctypes.c_void_p(0x10004)                       # 4-byte aligned: fine for FP32 arrays
+    assert L.ls_sketch_f32(hctx, S0, 100, 10, P, 10, P, 50, 8, 1, P4, 10, P4) == ls.LS_ERR_DEVICE
+    assert L.ls_sketch_f32(hctx, S0, 100, 10, P4, 10, P, 50, 8, 1, P4, 10, P4) == ls.LS_ERR_ARG  # A is FP64
+    assert L.ls_sketch_f32(hctx, S0, 100, 10, P, 10, P, 50, 8, 1, ctypes.c_void_p(0x10002), 10, P4) == ls.LS_ERR_ARG
+    assert L.ls_sketch_f32(hctx, S0, 100, 10, P, 10, NUL, 50, 8, 1, P4, 10, P4) == ls.LS_ERR_ARG  # b without Sb
+    assert L.ls_qr_sketch_f32(hctx, S0, 100, 10, P4, 10, P4, P4, 10, P) == ls.LS_ERR_DEVICE
+    assert L.ls_qr_sketch_f32(hctx, S0, 100, 10, P4, 10, P4, P4, 10, P4) == ls.LS_ERR_ARG    # x0 is FP64
+    assert L.ls_qr_sketch_f32(hctx, S0, 9, 10, P4, 10, P4, P4, 10, NUL) == ls.LS_ERR_ARG     # d < n
+    assert L.ls_precond_solve_f32(hctx, S0, 10, P4, 10, P, P) == ls.LS_ERR_DEVICE
+    assert L.ls_precond_solve_f32(hctx, S0, 10, P4, 9, P, P) == ls.LS_ERR_ARG
+    assert L.ls_solve(hctx, S0, 100, 10, P, 10, P, 200, 5, P) == ls.LS_ERR_DEVICE
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(ls, "_lib", None)
     monkeypatch.setattr(ls, "LIB_PATH", str(tmp_path / "libls.so"))
@@ -170,4 +189,6 @@ def test_stop_options(L, hctx):
     L.ls_get_option(hctx, ls.OPT_RHO, ctypes.byref(iv), ctypes.byref(dv))
     assert dv.value == 0.04
     d, q = ctypes.c_int64(), ctypes.c_int32()
-    assert L.ls_solve_info(hctx, ctypes.byref(d), ctypes.byref(q), None, None) == ls.LS_OK
+    pr = ctypes.c_int32(-1)
+    assert L.ls_solve_info(hctx, ctypes.byref(d), ctypes.byref(q), None, None, ctypes.byref(pr)) == ls.LS_OK
+    assert pr.value == ls.PRECISION_FP64

@@ -1,0 +1,222 @@
+"""GPU parity for the mixed-precision variant (FP32 sketch, QR and R-solves; FP64 pass and update),
+through the C ABI, against the oracle's mixed-precision functions on the same seeded inputs.
+
+The FP32 sketch is bit-exact (FP64 sums rounded once on both sides); the FP32 QR and solves are
+checked against single-precision backward-error bounds and the oracle's single-precision results;
+whole solves against FP64 accuracy (the point of refining with an FP32 factor) and the oracle's
+fallback decisions, and a fallback reproduces the FP64 solve bit for bit."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2311_04362_amd import ls  # noqa: E402
+from synth import ProblemSpec, make_problem_cpu  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ls.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+class Precision:
+    """Context option scope: mixed precision (and optionally the stopping rule) inside."""
+
+    def __init__(self, ctx, stop=0):
+        self.ctx, self.stop = ctx, stop
+
+    def __enter__(self):
+        self.ctx.set_option(ls.OPT_PRECISION, 1)
+        self.ctx.set_option(ls.OPT_STOP, self.stop)
+
+    def __exit__(self, *a):
+        self.ctx.set_option(ls.OPT_PRECISION, 0)
+        self.ctx.set_option(ls.OPT_STOP, 0)
+
+
+# --------------------------------------------------------------------------- FP32 sketch
+
+@pytest.mark.parametrize("m,n,d", [(1, 1, 1), (4099, 33, 1000), (3000, 65, 500), (20000, 500, 10000),
+                                   (2000, 1000, 2000)])
+def test_sketch_f32_is_rounded_fp64_sketch(ctx, m, n, d):
+    rng = np.random.default_rng(m + 2 * n + d)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    B, Sb = ctx.sketch_f32(dev(A), dev(b), d, 8 if d >= 8 else d, 17)
+    eB, eSb = oracle.sketch(A, b, n, d, 8 if d >= 8 else d, 17)
+    assert np.array_equal(host(B), eB.astype(np.float32))
+    assert np.array_equal(host(Sb), eSb.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------- FP32 QR
+
+@pytest.mark.parametrize("panel", [0, 1])
+@pytest.mark.parametrize("d,n,kappa", [(1, 1, 1.0), (100, 31, 1e2), (200, 33, 1e2), (1000, 50, 1e3),
+                                       (5000, 257, 1e2), (10000, 500, 1e3), (70000, 40, 1e3)])
+def test_qr_f32_vs_oracle(ctx, d, n, kappa, panel):
+    rng = np.random.default_rng(d * 5 + n)
+    Uq, _ = np.linalg.qr(rng.standard_normal((d, n)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    B = ((Uq * kappa ** (-np.arange(n) / max(n - 1, 1))) @ Vq.T).astype(np.float32)
+    Sb = rng.standard_normal(d).astype(np.float32)
+    ctx.set_option(ls.OPT_QR_PANEL, panel)
+    try:
+        R, x0 = ctx.qr_sketch_f32(dev(B), dev(Sb))
+        ctx.sync()
+    finally:
+        ctx.set_option(ls.OPT_QR_PANEL, 0)
+    R, x0 = host(R).astype(np.float64), host(x0)
+    xo, Ro, _ = oracle.householder_lstsq_f32(B, Sb)
+    B64, Ro = B.astype(np.float64), Ro.astype(np.float64)
+    nB = np.linalg.norm(B64)
+    assert np.all(np.tril(R, -1) == 0)
+    assert np.linalg.norm(R.T @ R - B64.T @ B64) <= 8 * n * U32 * nB ** 2     # single-precision QR
+    assert np.array_equal(np.sign(np.diag(R)), np.sign(np.diag(Ro)))
+    kap = np.linalg.cond(B64)
+    assert np.linalg.norm(R - Ro) <= 50 * n * U32 * kap * nB
+    # x0: both single-precision sketch-and-solve solutions of the same small problem
+    x64 = np.linalg.lstsq(B64, Sb.astype(np.float64), rcond=None)[0]
+    res = np.linalg.norm(B64 @ x64 - Sb)
+    tol = 100 * n * kap * U32 * (np.linalg.norm(x64) + kap * res / np.linalg.norm(B64, 2))
+    assert np.linalg.norm(x0 - x64) <= tol + 1e-30
+    assert np.linalg.norm(xo - x64) <= tol + 1e-30
+
+
+def test_qr_f32_panel_paths_agree_bitwise(ctx):
+    rng = np.random.default_rng(8)
+    B = dev(rng.standard_normal((3000, 70)).astype(np.float32))
+    Sb = dev(rng.standard_normal(3000).astype(np.float32))
+    R0, x0 = ctx.qr_sketch_f32(B, Sb)
+    ctx.set_option(ls.OPT_QR_PANEL, 1)
+    R1, x1 = ctx.qr_sketch_f32(B, Sb)
+    ctx.set_option(ls.OPT_QR_PANEL, 0)
+    assert torch.equal(R0, R1) and torch.equal(x0, x1)
+
+
+# ------------------------------------------------------------------------ FP32 R-solves
+
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (50, 1e2), (500, 1e3), (1000, 1e2), (2048, 1e2)])
+def test_precond_solve_f32_vs_oracle(ctx, n, kappa):
+    rng = np.random.default_rng(n + 3)
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    R = np.linalg.qr((Uq * kappa ** (-np.arange(n) / max(n - 1, 1))) @ Vq.T, mode="r").astype(np.float32)
+    c = rng.standard_normal(n) * 1e-7
+    d = host(ctx.precond_solve_f32(dev(R), dev(c)))
+    do = oracle.precond_f32(R, c)
+    R64 = R.astype(np.float64)
+    ref = np.linalg.solve(R64, np.linalg.solve(R64.T, c))
+    k = np.linalg.cond(R64)
+    assert np.linalg.norm(d - ref) <= 20 * n * k * U32 * np.linalg.norm(ref)
+    assert np.linalg.norm(d - do) <= 40 * n * k * U32 * np.linalg.norm(ref)
+    # exact power-of-two rescaling of c, also far outside the single-precision range
+    for e in (-700, 300):
+        assert torch.equal(ctx.precond_solve_f32(dev(R), dev(np.ldexp(c, e))).cpu(),
+                           torch.from_numpy(np.ldexp(d, e)))
+
+
+# ------------------------------------------------------------------------ whole solves
+
+@pytest.mark.parametrize("kappa,beta", [(1e1, 1e-6), (1e3, 1e-6), (1e5, 1e-3), (1e3, 1e-12)])
+def test_mixed_solve_reaches_fp64_accuracy(ctx, kappa, beta):
+    spec = ProblemSpec(m=4000, n=50, kappa=kappa, beta=beta, d=1000, seed=1)
+    p = make_problem_cpu(spec)
+    xo, used_o, _, _ = oracle.iterative_sketching_mixed(p.A, p.b, 50, 1000, 60, seed=spec.sketch_seed)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    with Precision(ctx):
+        x = host(ctx.solve(dev(p.A)[:, :50], dev(p.b), 1000, 60))
+        _, steps, ne, ce, used = ctx.solve_info()
+    assert used == ls.PRECISION_MIXED == used_o
+    assert steps == 60
+    assert ce * U32 <= 0.05
+    fe_h = np.linalg.norm(oracle.householder_lstsq(p.Aview, p.b)[0] - p.x_true)
+    assert np.linalg.norm(x - p.x_true) <= 10 * fe_h
+    assert np.linalg.norm(x - xo) <= 10 * fe_h
+
+
+def test_mixed_solve_deterministic(ctx):
+    p = make_problem_cpu(ProblemSpec(m=20000, n=300, kappa=1e3, beta=1e-6, d=6000, seed=2))
+    ctx.set_option(ls.OPT_SEED, p.spec.sketch_seed)
+    with Precision(ctx):
+        x1 = ctx.solve(dev(p.A)[:, :300], dev(p.b), 6000, 30)
+        x2 = ctx.solve(dev(p.A)[:, :300], dev(p.b), 6000, 30)
+    assert torch.equal(x1, x2)
+
+
+def test_mixed_falls_back_on_condest(ctx):
+    spec = ProblemSpec(m=4000, n=50, kappa=1e12, beta=1e-6, d=1000, seed=1)
+    p = make_problem_cpu(spec)
+    _, used_o, _, _ = oracle.iterative_sketching_mixed(p.A, p.b, 50, 1000, 30, seed=spec.sketch_seed)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    A, b = dev(p.A)[:, :50], dev(p.b)
+    x64 = ctx.solve(A, b, 1000, 30)
+    with Precision(ctx):
+        x = ctx.solve(A, b, 1000, 30)
+        _, steps, _, ce, used = ctx.solve_info()
+    assert used == ls.PRECISION_FELL_BACK_COND == used_o
+    assert ce * U32 > 0.05 and steps == 30
+    assert torch.equal(x, x64)                 # the fallback is the FP64 solve itself
+
+
+def test_mixed_falls_back_on_growth(ctx):
+    # d = n: the embedding is far from a subspace embedding and the iteration diverges, although
+    # the FP32 factor is well conditioned (Theorem 3.1 needs distortion below 0.29)
+    spec = ProblemSpec(m=2000, n=20, kappa=1e3, beta=1e-3, d=20, seed=0)
+    p = make_problem_cpu(spec)
+    _, used_o, _, _ = oracle.iterative_sketching_mixed(p.A, p.b, 20, 20, 30, seed=spec.sketch_seed)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    A, b = dev(p.A)[:, :20], dev(p.b)
+    x64 = ctx.solve(A, b, 20, 30)
+    with Precision(ctx):
+        x = ctx.solve(A, b, 20, 30)
+        _, steps, _, ce, used = ctx.solve_info()
+    assert used == ls.PRECISION_FELL_BACK_GROWTH == used_o
+    assert ce * U32 <= 0.05
+    assert torch.equal(x, x64)
+
+
+def test_mixed_with_stopping_rule(ctx):
+    spec = ProblemSpec(m=4000, n=50, kappa=1e4, beta=1e-6, d=1000, seed=5)
+    p = make_problem_cpu(spec)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    with Precision(ctx, stop=1):
+        x = host(ctx.solve(dev(p.A)[:, :50], dev(p.b), 1000, 200))
+        _, steps, ne, ce, used = ctx.solve_info()
+    assert used == ls.PRECISION_MIXED
+    assert 5 < steps < 200
+    assert abs(ne - np.linalg.norm(p.A[:, :50], 2)) <= 0.2 * ne   # ||R|| ~ ||A|| for an embedding
+    fe_h = np.linalg.norm(oracle.householder_lstsq(p.Aview, p.b)[0] - p.x_true)
+    assert np.linalg.norm(x - p.x_true) <= 10 * fe_h
+
+
+@pytest.mark.parametrize("update", [1, 2])
+def test_mixed_damping_momentum(ctx, update):
+    spec = ProblemSpec(m=4000, n=50, kappa=1e3, beta=1e-6, d=1000, seed=6)
+    p = make_problem_cpu(spec)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    ctx.set_option(ls.OPT_UPDATE, update)
+    try:
+        with Precision(ctx):
+            x = host(ctx.solve(dev(p.A)[:, :50], dev(p.b), 1000, 40))
+            used = ctx.solve_info()[4]
+    finally:
+        ctx.set_option(ls.OPT_UPDATE, 0)
+    assert used == ls.PRECISION_MIXED
+    fe_h = np.linalg.norm(oracle.householder_lstsq(p.Aview, p.b)[0] - p.x_true)
+    assert np.linalg.norm(x - p.x_true) <= 10 * fe_h

@@ -37,10 +37,10 @@ def test_stopping_rule_matches_oracle(ctx, kappa, beta):
     ctx.set_option(ls.OPT_STOP, 1)
     try:
         x = ctx.solve(dev(p.A)[:, :n], dev(p.b), d, 200).cpu().numpy()
-        d_used, steps, ne, ce = ctx.solve_info()
+        d_used, steps, ne, ce, prec = ctx.solve_info()
     finally:
         ctx.set_option(ls.OPT_STOP, 0)
-    assert d_used == d
+    assert d_used == d and prec == ls.PRECISION_FP64
     # normest: same start vector, same number of power steps; R agrees to rounding
     assert abs(ne - ne_o) <= 1e-8 * ne_o
     # condest: Hager's estimate; both are lower bounds of kappa_1(R) within its usual factor
@@ -61,9 +61,9 @@ def test_stopping_rule_fewer_steps_and_q_cap(ctx):
     ctx.set_option(ls.OPT_STOP, 1)
     try:
         ctx.solve(dev(p.A)[:, :50], dev(p.b), 1000, 200)
-        _, steps, _, _ = ctx.solve_info()
+        _, steps, _, _, _ = ctx.solve_info()
         ctx.solve(dev(p.A)[:, :50], dev(p.b), 1000, 5)        # the cap wins
-        _, steps5, _, _ = ctx.solve_info()
+        _, steps5, _, _, _ = ctx.solve_info()
     finally:
         ctx.set_option(ls.OPT_STOP, 0)
     assert 10 < steps < 200
@@ -81,7 +81,7 @@ def test_divergence_is_flagged(ctx):
         with pytest.raises(ls.LSError) as e:
             ctx.solve(dev(p.A)[:, :20], dev(p.b), 20, 100)
         assert e.value.status == ls.LS_ERR_DIVERGED
-        _, steps, _, _ = ctx.solve_info()
+        _, steps, _, _, _ = ctx.solve_info()
         assert steps < 100
     finally:
         ctx.set_option(ls.OPT_STOP, 0)
@@ -93,7 +93,7 @@ def test_dimension_rule(ctx, m, n):
     p = make_problem_cpu(ProblemSpec(m=m, n=n, kappa=1e2, beta=1e-6, seed=1))
     ctx.set_option(ls.OPT_SEED, p.spec.sketch_seed)
     x0 = ctx.solve(dev(p.A)[:, :n], dev(p.b), 0, 20)
-    d_used, steps, _, _ = ctx.solve_info()
+    d_used, steps, _, _, _ = ctx.solve_info()
     assert d_used == oracle.dimension(m, n)
     assert steps == 20
     x1 = ctx.solve(dev(p.A)[:, :n], dev(p.b), d_used, 20)
