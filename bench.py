@@ -7,6 +7,15 @@ JSON line: solves/s, the fused pass's achieved HBM bandwidth against the 8 TB/s 
 kernel time from HIP events on the launch stream), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Other workloads (one JSON line each):
+    --workload mixed_m1e6_n1000   mixed precision (FP32 sketch/QR/R-solves, FP64 pass/update) against
+                                  the FP64 solver on m = 1,000,000, n = 1000, d = 20,000 for
+                                  kappa in {1e2, 1e6, 1e12} x ||r|| in {1e-12, 1e-3, 1}: time and
+                                  forward error with the Section 3.3 stopping rule (equal forward
+                                  error: both stop at their accuracy floor) and at q = 40
+    --workload ls_large_m4e6_n2000  m = 4,000,000, n = 2000 (A is 64 GB), d = 40,000, q = 40, FP64
+                                  and mixed
 """
 from __future__ import annotations
 
@@ -26,6 +35,9 @@ WORKLOADS = {
     "ls_fp64_m2e6_n500": dict(m=2_000_000, n=500, d=10_000, zeta=8, q=40, kappa=1e10, beta=1e-6),
     # smaller shape for quick checks on the box
     "ls_fp64_m2e5_n500": dict(m=200_000, n=500, d=10_000, zeta=8, q=40, kappa=1e10, beta=1e-6),
+    "mixed_m1e6_n1000": dict(m=1_000_000, n=1000, d=20_000, zeta=8, q=40, kappas=(1e2, 1e6, 1e12),
+                             betas=(1e-12, 1e-3, 1.0), qmax=200),
+    "ls_large_m4e6_n2000": dict(m=4_000_000, n=2000, d=40_000, zeta=8, q=40, kappa=1e10, beta=1e-6),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_ls_fp64_m2e6_n500_traffic.json")
 
@@ -84,6 +96,125 @@ def cpu_baseline(w: dict, sample_rows: int):
                        f"-> {t_solve:.1f} s/solve")}
 
 
+def timed_solves(ctx, A, b, d, q, x, reps):
+    """Seconds per ls_solve (mean of reps after one warm-up) and the solve info of the last."""
+    import torch
+    ctx.solve(A, b, d, q, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.solve(A, b, d, q, x)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, ctx.solve_info()
+
+
+def bench_mixed(args, w):
+    """Mixed precision against FP64 on the nine (kappa, ||r||) cases of the m = 1e6, n = 1000 shape."""
+    import torch
+
+    from paper_2311_04362_amd import ls
+    from synth import ProblemSpec, make_problem_gpu
+
+    m, n, d, q = w["m"], w["n"], w["d"], w["q"]
+    ctx = ls.Context(0)
+    ctx.set_option(ls.OPT_ZETA, w["zeta"])
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    cases, speedups_stop, speedups_q = [], [], []
+    for kappa in w["kappas"]:
+        for beta in w["betas"]:
+            spec = ProblemSpec(m=m, n=n, kappa=kappa, beta=beta, d=d, q=q, zeta=w["zeta"], seed=0)
+            p = make_problem_gpu(spec)
+            A, b = p.A[:, :n], p.b
+            ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+            row = {"kappa": kappa, "residual_norm": beta}
+            for stop, qq, tag in ((1, w["qmax"], "stop"), (0, q, "q40")):
+                ctx.set_option(ls.OPT_STOP, stop)
+                for prec, name in ((0, "fp64"), (1, "mixed")):
+                    ctx.set_option(ls.OPT_PRECISION, prec)
+                    t, info = timed_solves(ctx, A, b, d, qq, x, args.steps)
+                    fe = float(torch.linalg.norm(x - p.x_true).item())
+                    row[f"{tag}_{name}"] = {"ms": 1e3 * t, "steps": info[1], "forward_error": fe,
+                                            "precision_used": ["fp64", "mixed", "fell_back_condest",
+                                                               "fell_back_growth"][info[4]],
+                                            "condest": info[3]}
+            ctx.set_option(ls.OPT_PRECISION, 0)
+            ctx.set_option(ls.OPT_STOP, 0)
+            row["speedup_stop"] = row["stop_fp64"]["ms"] / row["stop_mixed"]["ms"]
+            row["speedup_q40"] = row["q40_fp64"]["ms"] / row["q40_mixed"]["ms"]
+            speedups_stop.append(row["speedup_stop"])
+            speedups_q.append(row["speedup_q40"])
+            cases.append(row)
+            print(f"[bench] kappa={kappa:.0e} r={beta:.0e}: stop fp64 {row['stop_fp64']['ms']:.1f} ms "
+                  f"mixed {row['stop_mixed']['ms']:.1f} ms ({row['stop_mixed']['precision_used']}) "
+                  f"fe {row['stop_fp64']['forward_error']:.2e}/{row['stop_mixed']['forward_error']:.2e}",
+                  file=sys.stderr, flush=True)
+            del p, A, b
+            torch.cuda.empty_cache()
+    geo = math.exp(sum(math.log(v) for v in speedups_stop) / len(speedups_stop))
+    rec = {
+        "metric": "mixed/FP64 speedup at equal fwd error",
+        "value": geo,
+        "unit": "x (geometric mean over the nine cases, both with the Section 3.3 stopping rule)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": sum(c["stop_mixed"]["ms"] for c in cases) / len(cases),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "d": d, "zeta": w["zeta"],
+                   "qmax_stop": w["qmax"], "q_fixed": q},
+        "speedup_q40_geomean": math.exp(sum(math.log(v) for v in speedups_q) / len(speedups_q)),
+        "cases": cases,
+    }
+    print(json.dumps(rec))
+    ctx.close()
+
+
+def bench_large(args, w):
+    """One large problem (A = 64 GB) in FP64 and mixed precision."""
+    import torch
+
+    from paper_2311_04362_amd import ls
+    from synth import ProblemSpec, make_problem_gpu
+
+    m, n, d, q = w["m"], w["n"], w["d"], w["q"]
+    spec = ProblemSpec(m=m, n=n, kappa=w["kappa"], beta=w["beta"], d=d, q=q, zeta=w["zeta"], seed=0)
+    p = make_problem_gpu(spec)
+    A, b = p.A[:, :n], p.b
+    ctx = ls.Context(0)
+    ctx.set_option(ls.OPT_ZETA, w["zeta"])
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        ctx.set_option(ls.OPT_PRECISION, prec)
+        ctx.set_option(ls.OPT_PROFILE, 1)
+        ctx.profile(reset=True)
+        t, info = timed_solves(ctx, A, b, d, q, x, args.steps)
+        pass_ms, launches = ctx.profile(reset=True)
+        ctx.set_option(ls.OPT_PROFILE, 0)
+        per_launch = pass_ms / max(launches, 1)
+        out[name] = {"ms": 1e3 * t, "solves_per_s": 1.0 / t,
+                     "forward_error": float(torch.linalg.norm(x - p.x_true).item()),
+                     "precision_used": ["fp64", "mixed", "fell_back_condest", "fell_back_growth"][info[4]],
+                     "pass_GBps": pass_bytes(m, n) / (per_launch * 1e-3) / 1e9}
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    ctx.set_option(ls.OPT_PRECISION, 0)
+    achieved = out["fp64"]["pass_GBps"]
+    rec = {
+        "metric": "solves/s + iteration-pass HBM GB/s; mixed/FP64 speedup at equal fwd error",
+        "value": out["fp64"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": out["fp64"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "d": d, "zeta": w["zeta"], "q": q,
+                   "kappa": w["kappa"], "residual_norm": w["beta"]},
+        "roofline": {"bound": "hbm", "kernel": "k_pass (fused A^T(b - A x) pass)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "mixed": out["mixed"], "fp64": out["fp64"],
+        "mixed_speedup": out["fp64"]["ms"] / out["mixed"]["ms"],
+    }
+    print(json.dumps(rec))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,12 +231,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    w = WORKLOADS[args.workload]
+    if args.workload.startswith("mixed_"):
+        return bench_mixed(args, w)
+    if args.workload.startswith("ls_large_"):
+        return bench_large(args, w)
+
     import torch
 
     from paper_2311_04362_amd import ls
     from synth import ProblemSpec, make_problem_gpu
 
-    w = WORKLOADS[args.workload]
     m, n, d, q = w["m"], w["n"], w["d"], w["q"]
     spec = ProblemSpec(m=m, n=n, kappa=w["kappa"], beta=w["beta"], d=d, q=q, zeta=w["zeta"], seed=0)
     t_gen = time.perf_counter()

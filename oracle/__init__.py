@@ -87,6 +87,8 @@ def lib():
         L.orc_normest_f32.argtypes = [_i64, _F, _i64, _D, _i32]
         L.orc_condest_1_f32.restype = ctypes.c_double
         L.orc_condest_1_f32.argtypes = [_i64, _F, _i64]
+        L.orc_mixed_start_steps.restype = ctypes.c_int32
+        L.orc_mixed_start_steps.argtypes = [ctypes.c_double]
         L.orc_iterative_sketching_mixed.restype = ctypes.c_int
         L.orc_iterative_sketching_mixed.argtypes = [_i64, _i64, _D, _i64, _D, _i64, _i32, _u64, _i32,
                                                     _D, _F, _i64, _D, ctypes.POINTER(ctypes.c_int32)]
@@ -330,6 +332,11 @@ def normest_f32(R, g, steps: int) -> float:
 def condest_1_f32(R) -> float:
     R = _f32(R)
     return float(lib().orc_condest_1_f32(R.shape[0], _fp(R), R.shape[1]))
+
+
+def mixed_start_steps(condest: float) -> int:
+    """Refinement steps of the mixed-precision sketch-and-solve start for a given condest(R)."""
+    return int(lib().orc_mixed_start_steps(condest))
 
 
 def iterative_sketching_mixed(A, b, n: int, d: int, q: int, zeta: int = 8, seed: int = 0):

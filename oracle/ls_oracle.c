@@ -671,15 +671,31 @@ double orc_condest_1_f32(int64_t n, const float *R, int64_t ldr)
     return (double)n1 * (double)est;
 }
 
+/* Refinement steps of the sketch-and-solve start in the mixed reading: the single-precision QR
+ * solution x_0 is only single-precision accurate, while eq. (sketched_ls) defines x_0 as the exact
+ * minimizer of ||S b - S A x||; k0 steps of x <- x + orc_precond_f32(R, B^T (S b - B x)) on the
+ * double sketch (residual and update in double, as in the main loop) bring it to double accuracy.
+ * The contraction of these steps is about 2 condest(R) u_32, hence
+ *   k0 = ceil(ln(1e-9) / ln(2 condest u_32)), clamped to [2, 8]
+ * (from single-precision accuracy, about 1e-7, down to about 1e-16). */
+int32_t orc_mixed_start_steps(double condest)
+{
+    double rho = 2.0 * condest * ldexp(1.0, -24);
+    if (!(rho > 0.0)) return 2;
+    if (rho >= 0.5) return 8;
+    double k = ceil(log(1e-9) / log(rho));
+    return k < 2.0 ? 2 : (k > 8.0 ? 8 : (int32_t)k);
+}
+
 /* Algorithm 2 in mixed precision, with the fallback rule of this reading:
  *   B, S b (double, orc_sketch) -> rounded to float; single-precision Householder QR gives R and
  *   x_0; if condest(R) (orc_condest_1_f32) times u_32 = 2^-24 exceeds 0.05 (or is not finite), the
  *   single-precision factor is not trusted and the whole solve is redone in double
  *   (orc_iterative_sketching), *used = 2;
- *   otherwise q steps x <- x + orc_precond_f32(R, A^T (b - A x)) with the pass and the update in
- *   double; if ||r(x_i)||^2 grows three steps in a row, each time by more than a relative 2^-20
- *   (well above its rounding noise), or is not finite, the solve is redone in double, *used = 3;
- *   else *used = 1.
+ *   otherwise x_0 is refined on the double sketch (orc_mixed_start_steps), then q steps
+ *   x <- x + orc_precond_f32(R, A^T (b - A x)) with the pass and the update in double; if
+ *   ||r(x_i)||^2 grows three steps in a row, each time by more than a relative 2^-20 (well above its
+ *   rounding noise), or is not finite, the solve is redone in double, *used = 3; else *used = 1.
  * R_out (nullable, float, ldr) receives the single-precision R; rnorm2_hist (nullable, q) the
  * ||r_i||^2 of the mixed steps made.  Return codes as orc_iterative_sketching. */
 int orc_iterative_sketching_mixed(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
@@ -712,6 +728,12 @@ int orc_iterative_sketching_mixed(int64_t m, int64_t n, const double *A, int64_t
             *used = 2;
             rc = orc_iterative_sketching(m, n, A, lda, b, d, zeta, seed, q, x, NULL, NULL, 0, NULL);
             goto done;
+        }
+        int32_t k0 = orc_mixed_start_steps(ce);
+        for (int32_t k = 0; k < k0; ++k) {
+            orc_residual_gradient(d, n, B, n, Sb, x, c, NULL);
+            orc_precond_f32(n, R, n, c, dv);
+            for (int64_t l = 0; l < n; ++l) x[l] = x[l] + dv[l];
         }
     }
     {

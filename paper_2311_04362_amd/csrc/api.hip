@@ -207,9 +207,56 @@ ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes)
     return LS_OK;
 }
 
-// Algorithm 2 in FP64 (the body of ls_solve; also the fallback of the mixed path).
+// Refinement steps of Algorithm 2 in FP64 from x = x_0 with R (n x n, ld n) and RT = R^T: at most q
+// steps (ended on the device by the stopping rule when LS_OPT_STOP is set), then waits and returns
+// the deferred status.  ib must be sized for (m, n); est_work holds 3 n doubles.
+static ls_status iterate_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A,
+                              int64_t lda, const double *b, int64_t d, int32_t q, double *x,
+                              const double *R, const double *RT, const IterBufs &ib, double *est_work)
+{
+    int mode;
+    double alpha, beta;
+    update_params(ctx, n, d, mode, alpha, beta);
+    StopArgs st;
+    if (ctx->stop) {
+        HIP_TRY(ctx, launch_estimators(s, n, R, n, RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+        HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
+        st.state = ib.state;
+        st.scal = ib.scal;
+        st.dx = ib.dx;
+        st.gamma = ctx->gamma;
+        st.rho = ctx->rho;
+    }
+    if (mode == 2 && q > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
+    for (int32_t i = 0; i < q; ++i) {
+        if (ctx->stop) {
+            st.check = (i >= 1);
+            hipEvent_t e0, e1;
+            LS_TRY(pass_events(ctx, e0, e1));
+            HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
+                                         i >= 1 ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
+        } else {
+            LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
+        }
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
+    }
+    const ls_status status = ls_sync(ctx, s);
+    if (ctx->stop) {
+        int32_t stv[2];
+        double scv[4];
+        HIP_TRY(ctx, hipMemcpy(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost), "read steps");
+        HIP_TRY(ctx, hipMemcpy(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost), "read estimates");
+        ctx->last_steps = stv[1];
+        ctx->last_normest = scv[2];
+        ctx->last_condest = scv[3];
+    }
+    return status;
+}
+
+// Algorithm 2 in FP64 (the body of ls_solve).
 static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
-                     const double *b, int64_t d, int32_t q, double *x)
+                            const double *b, int64_t d, int32_t q, double *x)
 {
     const int32_t zeta = ctx->zeta;
     SketchBufs sb{};
@@ -232,71 +279,56 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
     // (c) q refinement steps (with the stopping rule: at most q, ended on the device).
-    int mode;
-    double alpha, beta;
-    update_params(ctx, n, d, mode, alpha, beta);
-    StopArgs st;
-    if (ctx->stop) {
-        HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
-        HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
-        st.state = ib.state;
-        st.scal = ib.scal;
-        st.dx = ib.dx;
-        st.gamma = ctx->gamma;
-        st.rho = ctx->rho;
-    }
-    if (mode == 2 && q > 0)
-        HIP_TRY(ctx, hipMemcpyAsync(ib.xprev, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s), "copy x");
-    for (int32_t i = 0; i < q; ++i) {
-        if (ctx->stop) {
-            st.check = (i >= 1);
-            hipEvent_t e0, e1;
-            LS_TRY(pass_events(ctx, e0, e1));
-            HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, ib.c, ib.scal, e0, e1,
-                                         i >= 1 ? ib.dx : nullptr, ib.scal + 1, ib.state), "pass kernels");
-        } else {
-            LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, ib.c, nullptr));
-        }
-        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ib.c, x, ib.xprev, nullptr, mode, alpha, beta, ctx->status, st), "solve kernel");
-    }
-    const ls_status status = ls_sync(ctx, s);
-    if (ctx->stop) {
-        int32_t stv[2];
-        double scv[4];
-        HIP_TRY(ctx, hipMemcpy(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost), "read steps");
-        HIP_TRY(ctx, hipMemcpy(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost), "read estimates");
-        ctx->last_steps = stv[1];
-        ctx->last_normest = scv[2];
-        ctx->last_condest = scv[3];
-    }
-    return status;
+    return iterate_fp64(ctx, s, m, n, A, lda, b, d, q, x, R, qb.RT, ib, est_work);
 }
 
+// Refinement steps of the mixed-precision sketch-and-solve start: the contraction of
+// x <- x + R32^{-1} R32^{-T} B^T (S b - B x) on the FP64 sketch is about 2 condest u_32, so
+// ceil(ln(1e-9) / ln(2 condest u_32)) steps, clamped to [2, 8], take the FP32 solution (about
+// 1e-7 relative) to FP64 accuracy.
+static int32_t mixed_start_steps(double condest)
+{
+    const double rho = 2.0 * condest * 0x1p-24;
+    if (!(rho > 0.0)) return 2;
+    if (rho >= 0.5) return 8;
+    const double k = std::ceil(std::log(1e-9) / std::log(rho));
+    return k < 2.0 ? 2 : (k > 8.0 ? 8 : (int32_t)k);
+}
 
-// Algorithm 2 with the FP32 sketch, QR and R-solves of the mixed-precision variant (the A^T (b-Ax)
-// pass and the update stay FP64).  Sets `used` to LS_PRECISION_MIXED when x is final, or to a
-// fallback reason, in which case the caller redoes the solve in FP64.  Waits on the stream after
-// the QR and the estimators (the fallback decision needs condest on the host) and at the end.
-static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A, int64_t lda,
-                      const double *b, int64_t d, int32_t q, double *x, int32_t &used)
+// Algorithm 2 with the FP32 sketch, QR and R-solves of the mixed-precision variant; the A^T (b-Ax)
+// pass and the update stay FP64.  The sketch is formed once in FP64 and rounded for the FP32 QR, so
+// the sketch-and-solve start can be refined on it in FP64 (eq. sketched_ls defines x_0 exactly) and
+// a fallback factors it in FP64 without sketching again.  Falls back when condest(R32) u_32 > 0.05
+// or the FP32 QR flags R (after the QR, on the host: one wait), or when ||r||^2 grows three steps
+// in a row (on the device, read at the end).  Sets `used` and leaves the final status to the caller.
+static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, const double *A,
+                             int64_t lda, const double *b, int64_t d, int32_t q, double *x, int32_t &used)
 {
     const int32_t zeta = ctx->zeta;
     SketchBufs sb{};
+    QrBufs qb64{};
     QrBufs32 qb{};
-    IterBufs ib{};
+    IterBufs ib{}, ibs{};
     float *R = nullptr, *est_work = nullptr;
+    double *Sb = nullptr, *R64 = nullptr, *est64 = nullptr;
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
         sketch_bufs(ar, m, d, zeta, sb);
+        qr_bufs(ar, d, n, qb64);
         qr_bufs(ar, d, n, qb);
         iter_bufs(ar, m, n, ib, false);
+        iter_bufs(ar, d, n, ibs, false);
         R = ar.take<float>((size_t)n * (size_t)n);
         est_work = ar.take<float>((size_t)3 * (size_t)n);
+        Sb = ar.take<double>((size_t)d);
+        R64 = ar.take<double>((size_t)n * (size_t)n);
+        est64 = ar.take<double>((size_t)3 * (size_t)n);
     }));
-    // (a) FP32 sketch straight into the QR work matrix (FP64 sums, rounded once).
+    // (a) FP64 sketch: B in the FP64 work matrix, S b contiguous; rounded copy for the FP32 QR.
     LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
-    // (b) FP32 QR, R, x0 by FP32 back substitution (widened), FP32 estimators.
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb64.W, qb64.ldw, Sb, 1), "gather kernel");
+    HIP_TRY(ctx, launch_round_sketch(s, d, n, qb64, Sb, qb), "round sketch");
+    // (b) FP32 QR, R, the FP32 start, FP32 estimators; the fallback decision on the host.
     HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
@@ -308,15 +340,25 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     ctx->last_normest = scv[2];
     ctx->last_condest = scv[3];
     const int32_t st0 = *ctx->status_host;
-    if ((st0 & (ST_RANK | ST_NONFINITE)) || !(scv[3] * 0x1p-24 <= 0.05)) {
-        if (st0 != 0) {
-            HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
-            HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
-        }
-        used = LS_PRECISION_FELL_BACK_COND;
-        return LS_OK;
+    // FP64 solve from the FP64 sketch (the fallback): set S b as column n, factor, iterate.
+    auto fallback = [&](int32_t why) -> ls_status {
+        used = why;
+        ctx->last_steps = q;
+        HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
+        HIP_TRY(ctx, launch_set_rhs(s, d, n, Sb, qb64), "set rhs");
+        HIP_TRY(ctx, launch_qr(s, d, n, qb64, ctx->status, ctx->qr_panel == 1), "QR kernels");
+        HIP_TRY(ctx, launch_extract_r(s, n, qb64, R64, n, ctx->status), "extract R");
+        HIP_TRY(ctx, launch_back_substitution(s, n, R64, n, qb64.RT, qb64.qtb, x, ctx->status), "x0 solve");
+        return iterate_fp64(ctx, s, m, n, A, lda, b, d, q, x, R64, qb64.RT, ib, est64);
+    };
+    if ((st0 & (ST_RANK | ST_NONFINITE)) || !(scv[3] * 0x1p-24 <= 0.05)) return fallback(LS_PRECISION_FELL_BACK_COND);
+    // (c) the start to FP64 accuracy on the FP64 sketch (B still intact in qb64.W).
+    const int32_t k0 = mixed_start_steps(scv[3]);
+    for (int32_t k = 0; k < k0; ++k) {
+        HIP_TRY(ctx, launch_gradient(s, d, n, qb64.W, qb64.ldw, Sb, x, ibs, ibs.c, nullptr), "start pass");
+        HIP_TRY(ctx, launch_solve_update(s, n, R, n, qb.RT, ibs.c, x, nullptr, nullptr, 1, 1.0, 0.0, ctx->status), "start solve");
     }
-    // (c) q refinement steps: FP64 pass, FP32 solves, FP64 update, growth monitor on the device.
+    // (d) q refinement steps: FP64 pass, FP32 solves, FP64 update, growth monitor on the device.
     int mode;
     double alpha, beta;
     update_params(ctx, n, d, mode, alpha, beta);
@@ -343,12 +385,9 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     HIP_TRY(ctx, hipMemcpyAsync(stv, ib.state, sizeof(stv), hipMemcpyDeviceToHost, s), "read steps");
     HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
     ctx->last_steps = stv[1];
-    if (stv[2]) {                      // the FP64 solve starts from a clean status word
-        used = LS_PRECISION_FELL_BACK_GROWTH;
-        HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
-        HIP_TRY(ctx, hipStreamSynchronize(s), "stream synchronize");
-    }
-    return LS_OK;
+    if (stv[2]) return fallback(LS_PRECISION_FELL_BACK_GROWTH);
+    used = LS_PRECISION_MIXED;
+    return ls_sync(ctx, s);
 }
 
 extern "C" {
@@ -736,10 +775,9 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
     ctx->last_precision = LS_PRECISION_FP64;
     if (ctx->precision == 1) {
         int32_t used = LS_PRECISION_MIXED;
-        LS_TRY(solve_mixed(ctx, s, m, n, A, lda, b, d, q, x, used));
+        const ls_status st = solve_mixed(ctx, s, m, n, A, lda, b, d, q, x, used);
         ctx->last_precision = used;
-        if (used == LS_PRECISION_MIXED) return ls_sync(ctx, stream);
-        ctx->last_steps = q;
+        return st;
     }
     return solve_fp64(ctx, s, m, n, A, lda, b, d, q, x);
 }

@@ -140,6 +140,11 @@ hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double 
                               const double *Sb, const QrBufs &qb);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *B, int64_t ldb,
                               const float *Sb, const QrBufs32 &qb);
+// Mixed path: qb32.W = [fl32(B) | fl32(Sb)] with B in qb64.W's first n columns and Sb contiguous;
+// launch_set_rhs puts Sb into column n of qb64.W (the FP64 fallback).
+hipError_t launch_round_sketch(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb64, const double *Sb,
+                               const QrBufs32 &qb32);
+hipError_t launch_set_rhs(hipStream_t s, int64_t d, int64_t n, const double *Sb, const QrBufs &qb);
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
                      bool per_column = false);
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs32 &qb, int32_t *status,

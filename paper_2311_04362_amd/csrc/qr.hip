@@ -15,6 +15,8 @@
 // V^T C is split over row chunks whose partial products are summed in a fixed order, so the
 // factorization is deterministic.  Every kernel is instantiated for FP64 and FP32.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 
@@ -58,8 +60,12 @@ __device__ __forceinline__ E wave_transpose_sum(E (&v)[kNB], int lane)
         const bool upper = (lane & off) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            const E send = upper ? v[i] : v[i + half];
-            const E keep = upper ? v[i + half] : v[i];
+            // The empty asm keeps the two values opaque: otherwise the compiler folds the selects
+            // below into one load with a lane-dependent index, which moves v to scratch memory.
+            E lo = v[i], hi = v[i + half];
+            asm volatile("" : "+v"(lo), "+v"(hi));
+            const E send = upper ? lo : hi;
+            const E keep = upper ? hi : lo;
             v[i] = keep + __shfl_xor(send, off, 64);
         }
     }
@@ -204,6 +210,13 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 // bound is ever reached the kernel flags ST_TIMEOUT and runs to completion, so it always exits.
 constexpr unsigned kSpinLimit = 1u << 20;
 
+// Calls f(std::integral_constant<int, J>{}) for J = 0, 1, ... in order.
+template <class F, int... J>
+__device__ __forceinline__ void for_each_column(F &f, std::integer_sequence<int, J...>)
+{
+    (f(std::integral_constant<int, J>{}), ...);
+}
+
 // Grid barrier by per-work-group step flags: after publishing its data, work-group g stores
 // flag[g] = epoch with release semantics; the barrier waits until every flag has reached epoch.
 // Flags only grow, so they need no reset within a launch.  The wait is bounded: past kSpinLimit
@@ -250,18 +263,19 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
     int64_t row[RPT];
     bool ok[RPT];
     E w[RPT][kNB];
-    E vv[RPT][kNB];                                    // Householder vectors, row by row
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * kRB + tid;
         ok[r] = row[r] < d;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) {
-            w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : E(0);
-            vv[r][l] = E(0);
-        }
+        for (int l = 0; l < kNB; ++l) w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : E(0);
     }
-    for (int jc = 0; jc < nbp; ++jc) {
+    // One column step.  The steps are expanded at compile time (for_each_column below, always
+    // inlined), so every register index is static -- a runtime index would put the row arrays in
+    // scratch memory or behind select chains.
+    auto column = [&](auto jcc) __attribute__((always_inline)) {
+        constexpr int jc = decltype(jcc)::value;
+        if (jc >= nbp) return;
         const int64_t k = p0 + jc;
         const int pb = jc & 1;
         E *rb = red + (int64_t)pb * nwg * kNB;
@@ -272,14 +286,10 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             for (int l = 0; l < kNB; ++l) pv[l] = E(0);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                E wj = E(0);
-#pragma unroll
-                for (int q = 0; q < kNB; ++q)
-                    if (q == jc) wj = w[r][q];
                 const bool use = ok[r] && row[r] >= k;
 #pragma unroll
-                for (int l = 0; l < kNB; ++l)
-                    if (use && l >= jc && l < nbp) pv[l] += wj * w[r][l];
+                for (int l = jc; l < kNB; ++l)
+                    if (use && l < nbp) pv[l] += w[r][jc] * w[r][l];
             }
             const E tot = wave_transpose_sum(pv, lane);
             if ((lane & 1) == 0) s_part[wave][tidx] = tot;
@@ -346,34 +356,28 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             }
         }
         __syncthreads();
+        // (4) apply the reflector to my rows; entry jc of each row's Householder vector goes to V
+        // (zero for rows above the pivot)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (!ok[r] || row[r] < k) continue;
-            E wjc = E(0);
+            if (!ok[r]) continue;
+            const bool below = row[r] >= k;
+            const E vi = (row[r] == k) ? s_scal[1] : w[r][jc];
+            V[(row[r] - p0) * kNB + jc] = below ? vi : E(0);
+            if (!below) continue;
 #pragma unroll
-            for (int q = 0; q < kNB; ++q)
-                if (q == jc) wjc = w[r][q];
-            const E vi = (row[r] == k) ? s_scal[1] : wjc;
-#pragma unroll
-            for (int l = 0; l < kNB; ++l)
-                if (l > jc && l < nbp) w[r][l] -= s_f[l] * vi;
-#pragma unroll
-            for (int l = 0; l < kNB; ++l)
-                if (l == jc) {
-                    vv[r][l] = vi;
-                    w[r][l] = (row[r] == k) ? s_scal[0] : E(0);
-                }
+            for (int l = jc + 1; l < kNB; ++l)
+                if (l < nbp) w[r][l] -= s_f[l] * vi;
+            w[r][jc] = (row[r] == k) ? s_scal[0] : E(0);
         }
-    }
+    };
+    for_each_column(column, std::make_integer_sequence<int, kNB>{});
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         if (!ok[r]) continue;
-        E *vrow = V + (row[r] - p0) * kNB;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) {
+        for (int l = 0; l < kNB; ++l)
             if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
-            vrow[l] = vv[r][l];
-        }
     }
 }
 
@@ -534,6 +538,27 @@ k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restric
     }
 }
 
+// Mixed path: W32 = [fl32(B) | fl32(Sb)] from the FP64 sketch (B in W64's first n columns, Sb
+// contiguous), each entry rounded once.
+__global__ void __launch_bounds__(256)
+k_round_sketch(int64_t d, int64_t n, const double *__restrict__ B, int64_t ldb,
+               const double *__restrict__ Sb, float *__restrict__ W, int64_t ldw)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = n + 1;
+    if (e >= d * w) return;
+    const int64_t i = e / w, c = e % w;
+    W[i * ldw + c] = (float)((c < n) ? B[i * ldb + c] : Sb[i]);
+}
+
+// Column n of the FP64 work matrix = Sb (the mixed path's fallback to the FP64 QR).
+__global__ void __launch_bounds__(256)
+k_set_rhs(int64_t d, int64_t n, const double *__restrict__ Sb, double *__restrict__ W, int64_t ldw)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d) W[i * ldw + n] = Sb[i];
+}
+
 template <typename E>
 __global__ void __launch_bounds__(256)
 k_copy_sketch(int64_t d, int64_t n, const E *__restrict__ B, int64_t ldb,
@@ -640,6 +665,21 @@ hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *
                               const float *Sb, const QrBufs32 &qb)
 {
     return copy_sketch_impl(s, d, n, B, ldb, Sb, qb);
+}
+
+hipError_t launch_round_sketch(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb64, const double *Sb,
+                               const QrBufs32 &qb32)
+{
+    const int64_t total = d * (n + 1);
+    hipLaunchKernelGGL(k_round_sketch, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, d, n,
+                       (const double *)qb64.W, qb64.ldw, Sb, qb32.W, qb32.ldw);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_rhs(hipStream_t s, int64_t d, int64_t n, const double *Sb, const QrBufs &qb)
+{
+    hipLaunchKernelGGL(k_set_rhs, dim3((unsigned)ceil_div(d, 256)), dim3(256), 0, s, d, n, Sb, qb.W, qb.ldw);
+    return hipGetLastError();
 }
 
 namespace {

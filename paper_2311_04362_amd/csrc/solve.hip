@@ -611,21 +611,16 @@ k_estimators(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restric
     if (steps < 1) steps = 1;
     T est = T(0);
     for (int it = 0; it < steps; ++it) {
-        for (int64_t i = wave; i < n; i += nw) {            // w = R v, one row per wave
-            T a = T(0);
-            for (int64_t k = i + lane; k < n; k += 64) a += R[i * ldr + k] * v[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-            if (lane == 0) w[i] = a;
-        }
+        for (int64_t i = tid; i < n; i += blockDim.x)       // w = R v, one row per thread, read as
+            w[i] = strided_dot<8>(RT + i * n + i, n, v + i, (int)(n - i));   // a column of R^T
+
         __syncthreads();
         T ww = T(0);
         for (int64_t i = tid; i < n; i += blockDim.x) ww += w[i] * w[i];
         est = sqrt(block_sum(ww, red));
         T vv = T(0);
         for (int64_t k = tid; k < n; k += blockDim.x) {      // v = R^T w, one column per thread
-            T a = T(0);
-            for (int64_t i = 0; i <= k; ++i) a += R[i * ldr + k] * w[i];
+            const T a = strided_dot<8>(R + k, ldr, (const T *)w, (int)(k + 1));
             v[k] = a;
             vv += a * a;
         }
@@ -636,9 +631,17 @@ k_estimators(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restric
     }
     // ---- condest
     T n1 = T(0);
-    for (int64_t k = tid; k < n; k += blockDim.x) {
+    for (int64_t k = tid; k < n; k += blockDim.x) {        // column 1-norms, 8 loads in flight
         T a = T(0);
-        for (int64_t i = 0; i <= k; ++i) a += fabs(R[i * ldr + k]);
+        int64_t i = 0;
+        for (; i + 8 <= k + 1; i += 8) {
+            T t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = R[(i + u) * ldr + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += fabs(t[u]);
+        }
+        for (; i <= k; ++i) a += fabs(R[i * ldr + k]);
         n1 = fmax(n1, a);
     }
 #pragma unroll

@@ -605,3 +605,22 @@ def test_mixed_growth_monitor_falls_back():
     assert oracle.condest_1_f32(R32) * U32 <= 0.05
     assert rn[1] > rn[0] and rn[2] > rn[1] and rn[3] > rn[2]
     assert np.array_equal(x, oracle.iterative_sketching(p.A, p.b, 20, 20, 40, seed=spec.sketch_seed))
+
+
+@pytest.mark.parametrize("kappa,beta", [(1e1, 1e-12), (1e3, 1e-3), (1e5, 1e-12)])
+def test_mixed_start_is_fp64_sketch_and_solve(kappa, beta):
+    """With q = 0 the mixed solve returns its refined start: the minimizer of ||S b - S A x|| of
+    eq. (sketched_ls) to double accuracy (the double Householder solution of the same sketch),
+    although its factor is single precision."""
+    spec = ProblemSpec(m=8000, n=100, kappa=kappa, beta=beta, d=2000, seed=3)
+    p = make_problem_cpu(spec)
+    x, used, R32, _ = oracle.iterative_sketching_mixed(p.A, p.b, 100, 2000, 0, seed=spec.sketch_seed)
+    assert used == oracle.MIXED
+    B, Sb = oracle.sketch(p.A, p.b, 100, 2000, 8, spec.sketch_seed)
+    xh, _, _, res = oracle.householder_lstsq(B, Sb)
+    kap = np.linalg.cond(B)
+    floor = kap * U * (np.linalg.norm(xh) + kap * res / np.linalg.norm(B, 2))
+    assert np.linalg.norm(x - xh) <= 100 * floor
+    x32, _, _ = oracle.householder_lstsq_f32(B, Sb)
+    assert np.linalg.norm(x32 - xh) >= 1e4 * floor        # the unrefined FP32 start is not
+    assert 2 <= oracle.mixed_start_steps(oracle.condest_1_f32(R32)) <= 8
