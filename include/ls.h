@@ -40,7 +40,8 @@ typedef enum {
     LS_ERR_RANK = 4,         /* deferred: |R_kk| <= n u max_j |R_jj| (A taken as rank deficient) */
     LS_ERR_NONFINITE = 5,    /* deferred: NaN or Inf met in B, R or x                            */
     LS_ERR_DIVERGED = 6,     /* deferred: the stopping rule saw the residual grow without bound  */
-    LS_ERR_UNSUPPORTED = 7   /* a size outside what this build handles (see ls_limits)           */
+    LS_ERR_UNSUPPORTED = 7,  /* a size outside what this build handles (see ls_limits)           */
+    LS_ERR_TIMEOUT = 8       /* ls_server_wait: the request did not finish within the timeout    */
 } ls_status;
 
 typedef struct ls_ctx ls_ctx;
@@ -193,6 +194,39 @@ ls_status ls_qr_sketch_f32(ls_ctx *ctx, void *stream, int64_t d, int64_t n, cons
  * by a power of two as above; c and d are FP64. */
 ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float *R, int64_t ldr,
                                const double *c, double *d);
+
+/* ---- Served stream (many independent solves resident on one GPU) -------------------------------
+ * A server solves submitted problems with ls_solve's FP64 algorithm (zeta = 8, fixed q, plain update)
+ * and returns, for each, the same bits ls_solve returns for it alone.  Problems are admitted first
+ * in, first out while the sum of the footprints 8mn + 8m + 8n^2 + 4 zeta m + 8dn of the admitted
+ * problems stays within `budget_bytes` and at most `max_active` are admitted; the sketch, QR and
+ * start of each are computed on a setup stream, one problem after another, and then every
+ * admitted problem takes one refinement step per round on a serve stream (one batched launch per
+ * kernel for all of them: continuous batching -- problems join and leave between rounds).  A
+ * scheduler thread owned by the server does all device work.  A, b and x are device pointers owned
+ * by the caller: A and b must stay unchanged and x untouched until the request is finished; x then
+ * holds x_q.  ls_server_submit and ls_server_wait may be called from any host thread.
+ * 1 <= max_active <= 4096.  device = -1 creates a host-only server for argument checks (submit
+ * returns LS_ERR_DEVICE). */
+typedef struct ls_server ls_server;
+ls_status ls_server_create(int device, int64_t budget_bytes, int32_t max_active, ls_server **out);
+/* Finishes every submitted request, then frees the server. */
+void ls_server_destroy(ls_server *server);
+/* Queues one solve (arguments as ls_solve; d >= n) and returns its ticket.  LS_ERR_ALLOC if its
+ * footprint alone exceeds the budget.  Never blocks on the device. */
+ls_status ls_server_submit(ls_server *server, int64_t m, int64_t n, const double *A, int64_t lda,
+                           const double *b, int64_t d, int32_t q, uint64_t seed, double *x,
+                           int64_t *ticket);
+/* Waits until the request is finished (timeout_s < 0: no limit) and stores its status (LS_OK, or a
+ * deferred error of that problem alone) in *result; LS_ERR_TIMEOUT if it is still running. */
+ls_status ls_server_wait(ls_server *server, int64_t ticket, double timeout_s, ls_status *result);
+/* times[0..3]: submission, admission, first round, completion (seconds since ls_server_create;
+ * completion is when the scheduler saw the last round end). */
+ls_status ls_server_request_info(ls_server *server, int64_t ticket, double *times);
+/* stats[0..6]: submitted, finished, queued, admitted and unfinished, footprint now, peak footprint,
+ * rounds launched. */
+ls_status ls_server_stats(ls_server *server, int64_t *stats);
+const char *ls_server_last_error(ls_server *server);
 
 /* Waits for `stream`, then returns and clears the deferred device status of the context. */
 ls_status ls_sync(ls_ctx *ctx, void *stream);

@@ -168,6 +168,28 @@ struct IterBufs {
     int32_t P;
 };
 int32_t iter_partials(int64_t m, int64_t n);
+
+// ---- served rounds (pass.hip, solve.hip; driven by server.hip) ----------------------------------
+// One resident problem of a served round.  Its pass runs as virtual work-groups 0..P-1 (P =
+// iter_partials(m, n)), its reduction as column blocks 0..ceil(n/64)-1, its solve as one
+// work-group, with exactly the arithmetic of ls_iterate on it alone.
+struct ServeSlot {
+    const double *A, *b;
+    double *x;                  // x_i in, x_{i+1} out (the caller's buffer)
+    const double *R, *RT;       // n x n, ld n, zero strict lower triangle; RT = R^T
+    double *part, *part_rr;     // P x n, P
+    double *c, *rr;             // n, 1
+    int64_t m, n, lda;
+    int32_t P, pass_base, red_base, cls;
+    int32_t *status;            // the problem's own status word
+};
+int32_t pass_class(int64_t n);  // pass variant of a problem with n columns (0..8)
+// Pass of every slot of class `cls` (work-groups listed in wg_slot, total_wg of them), reductions of
+// every slot, and the solve + update x += d of every slot (one work-group each).
+hipError_t launch_served_pass(hipStream_t s, int cls, int total_wg, const ServeSlot *slots,
+                              const int32_t *wg_slot);
+hipError_t launch_served_reduce(hipStream_t s, int total_wg, const ServeSlot *slots, const int32_t *wg_slot);
+hipError_t launch_served_solve(hipStream_t s, int nslots, int64_t max_n, const ServeSlot *slots);
 void iter_bufs(Arena &ar, int64_t m, int64_t n, IterBufs &ib, bool need_rt);
 hipError_t launch_transpose(hipStream_t s, int64_t n, const double *R, int64_t ldr, double *RT);
 hipError_t launch_transpose(hipStream_t s, int64_t n, const float *R, int64_t ldr, float *RT);

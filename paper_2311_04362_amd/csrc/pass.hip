@@ -30,12 +30,11 @@ __device__ __forceinline__ double group_sum(double v)
 // dx = x_i - x_{i-1} that is ||r(x_{i-1}) - r(x_i)||^2, the left side of the stopping rule.
 // A non-null `done` flag that is set makes the launch a no-op (the stopping rule has fired).
 template <int G, int CPL, int RT, bool DX>
-__global__ void __launch_bounds__(kPassThreads)
-k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
-       const double *__restrict__ x, double *__restrict__ part, double *__restrict__ part_rr,
-       const double *__restrict__ dx, double *__restrict__ part_ad, const int32_t *__restrict__ done)
+__device__ __forceinline__ void
+pass_body(int vblock, int vgrid, int64_t m, int64_t n, const double *__restrict__ A, int64_t lda,
+          const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ part,
+          double *__restrict__ part_rr, const double *__restrict__ dx, double *__restrict__ part_ad)
 {
-    if (done && *done) return;
     constexpr int RPW = 64 / G;
     constexpr int TILE = RPW * RT;                   // rows per wave per tile
     constexpr int WAVES = kPassThreads / 64;
@@ -59,8 +58,8 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
     for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
     double rr = 0.0, ad = 0.0;
 
-    const int64_t step = (int64_t)gridDim.x * WAVES * TILE;
-    for (int64_t t0 = ((int64_t)blockIdx.x * WAVES + wave) * TILE; t0 < m; t0 += step) {
+    const int64_t step = (int64_t)vgrid * WAVES * TILE;
+    for (int64_t t0 = ((int64_t)vblock * WAVES + wave) * TILE; t0 < m; t0 += step) {
         double a[RT][CPL];
         double bb[RT];
 #pragma unroll
@@ -116,34 +115,55 @@ k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const do
         __syncthreads();
     }
     for (int col = threadIdx.x; col < G * CPL; col += kPassThreads)
-        if (col < n) part[(int64_t)blockIdx.x * n + col] = s_acc[col];
+        if (col < n) part[(int64_t)vblock * n + col] = s_acc[col];
     if (threadIdx.x == 0) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) s += s_rr[w];
-        part_rr[blockIdx.x] = s;
+        part_rr[vblock] = s;
         if (DX) {
             double t = 0.0;
 #pragma unroll
             for (int w = 0; w < WAVES; ++w) t += s_ad[w];
-            part_ad[blockIdx.x] = t;
+            part_ad[vblock] = t;
         }
     }
+}
+
+template <int G, int CPL, int RT, bool DX>
+__global__ void __launch_bounds__(kPassThreads)
+k_pass(int64_t m, int64_t n, const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
+       const double *__restrict__ x, double *__restrict__ part, double *__restrict__ part_rr,
+       const double *__restrict__ dx, double *__restrict__ part_ad, const int32_t *__restrict__ done)
+{
+    if (done && *done) return;
+    pass_body<G, CPL, RT, DX>(blockIdx.x, gridDim.x, m, n, A, lda, b, x, part, part_rr, dx, part_ad);
+}
+
+// Served rounds: the pass of many resident problems in one launch.  Work-group w runs virtual
+// work-group w - pass_base of problem wg_slot[w], out of that problem's own P partials, so each
+// problem's arithmetic is exactly that of k_pass on it alone (ls_solve / ls_iterate).
+template <int G, int CPL, int RT>
+__global__ void __launch_bounds__(kPassThreads)
+k_pass_served(const ServeSlot *__restrict__ slots, const int32_t *__restrict__ wg_slot)
+{
+    const ServeSlot &sl = slots[wg_slot[blockIdx.x]];
+    pass_body<G, CPL, RT, false>((int)blockIdx.x - sl.pass_base, sl.P, sl.m, sl.n, sl.A, sl.lda, sl.b,
+                                 sl.x, sl.part, sl.part_rr, nullptr, nullptr);
 }
 
 // c[col] = sum_p part[p][col] in a fixed order: 16 contiguous groups of partials, each summed in
 // ascending p, then the 16 group sums in order.  Work-group 0 also reduces ||r||^2 likewise.
 constexpr int kRedGroups = 16;
 
-__global__ void __launch_bounds__(64 * kRedGroups)
-k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__restrict__ part_rr,
-         double *__restrict__ c, double *__restrict__ rr_out, const double *__restrict__ part_ad,
-         double *__restrict__ ad_out, const int32_t *__restrict__ done)
+__device__ __forceinline__ void
+reduce_body(int vblock, int32_t P, int64_t n, const double *__restrict__ part,
+            const double *__restrict__ part_rr, double *__restrict__ c, double *__restrict__ rr_out,
+            const double *__restrict__ part_ad, double *__restrict__ ad_out)
 {
-    if (done && *done) return;
     __shared__ double s[kRedGroups][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t col = (int64_t)vblock * 64 + lane;
     const int32_t per = (P + kRedGroups - 1) / kRedGroups;
     const int32_t p_lo = g * per;
     const int32_t cnt = (p_lo + per < P) ? per : (P > p_lo ? P - p_lo : 0);
@@ -155,7 +175,7 @@ k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__
         for (int q = 0; q < kRedGroups; ++q) t += s[q][lane];
         c[col] = t;
     }
-    if (blockIdx.x == 0 && rr_out) {
+    if (vblock == 0 && rr_out) {
         __syncthreads();
         if (lane == 0) s[g][0] = strided_sum<8>(part_rr + p_lo, cnt, 1);
         if (lane == 1 && part_ad) s[g][1] = strided_sum<8>(part_ad + p_lo, cnt, 1);
@@ -170,6 +190,24 @@ k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(64 * kRedGroups)
+k_reduce(int32_t P, int64_t n, const double *__restrict__ part, const double *__restrict__ part_rr,
+         double *__restrict__ c, double *__restrict__ rr_out, const double *__restrict__ part_ad,
+         double *__restrict__ ad_out, const int32_t *__restrict__ done)
+{
+    if (done && *done) return;
+    reduce_body(blockIdx.x, P, n, part, part_rr, c, rr_out, part_ad, ad_out);
+}
+
+// Served rounds: the reductions of many problems in one launch (work-group w does column block
+// w - red_base of problem wg_slot[w]).
+__global__ void __launch_bounds__(64 * kRedGroups)
+k_reduce_served(const ServeSlot *__restrict__ slots, const int32_t *__restrict__ wg_slot)
+{
+    const ServeSlot &sl = slots[wg_slot[blockIdx.x]];
+    reduce_body((int)blockIdx.x - sl.red_base, sl.P, sl.n, sl.part, sl.part_rr, sl.c, sl.rr, nullptr, nullptr);
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -228,6 +266,43 @@ void pass_launch(hipStream_t s, int P, int64_t m, int64_t n, const double *A, in
 }
 
 }  // namespace
+
+int32_t pass_class(int64_t n) { return pass_variant(n).id; }
+
+namespace {
+
+template <int G, int CPL, int RT>
+void served_pass_launch(hipStream_t s, int total_wg, const ServeSlot *slots, const int32_t *wg_slot)
+{
+    hipLaunchKernelGGL((k_pass_served<G, CPL, RT>), dim3(total_wg), dim3(kPassThreads), 0, s, slots, wg_slot);
+}
+
+}  // namespace
+
+hipError_t launch_served_pass(hipStream_t s, int cls, int total_wg, const ServeSlot *slots,
+                              const int32_t *wg_slot)
+{
+    if (total_wg <= 0) return hipSuccess;
+    switch (cls) {                        // the classes of pass_variant
+    case 0: served_pass_launch<8, 1, 4>(s, total_wg, slots, wg_slot); break;
+    case 1: served_pass_launch<16, 1, 4>(s, total_wg, slots, wg_slot); break;
+    case 2: served_pass_launch<16, 2, 4>(s, total_wg, slots, wg_slot); break;
+    case 3: served_pass_launch<16, 4, 4>(s, total_wg, slots, wg_slot); break;
+    case 4: served_pass_launch<64, 2, 4>(s, total_wg, slots, wg_slot); break;
+    case 5: served_pass_launch<64, 4, 4>(s, total_wg, slots, wg_slot); break;
+    case 6: served_pass_launch<64, 8, 4>(s, total_wg, slots, wg_slot); break;
+    case 7: served_pass_launch<64, 16, 2>(s, total_wg, slots, wg_slot); break;
+    default: served_pass_launch<64, 32, 1>(s, total_wg, slots, wg_slot); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_served_reduce(hipStream_t s, int total_wg, const ServeSlot *slots, const int32_t *wg_slot)
+{
+    if (total_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_served, dim3(total_wg), dim3(64 * kRedGroups), 0, s, slots, wg_slot);
+    return hipGetLastError();
+}
 
 int32_t iter_partials(int64_t m, int64_t n)
 {

@@ -1,0 +1,653 @@
+// Served stream of least-squares solves: many independent problems min ||b - A x|| resident on one
+// GPU, admitted by HBM footprint, set up (sketch, QR, sketch-and-solve start) one after another on
+// a setup stream, and iterated together in rounds on a serve stream.  A round is one refinement
+// step (Algorithm 2 loop body) of every resident problem: one batched pass launch per pass class,
+// one batched reduction and one batched solve + update (pass.hip, solve.hip).  Problems join at the
+// next round after their setup and leave after their q-th (continuous batching), so the launch cost
+// of a round is shared by everything resident.  Each problem's arithmetic is that of ls_solve on it
+// alone: its result does not depend on what else is resident.
+//
+// A scheduler thread owned by the server does all device work; ls_server_submit and ls_server_wait
+// may be called from any host thread.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kRoundsInFlight = 2;     // rounds enqueued ahead of the host
+constexpr int kClasses = 9;            // pass classes (pass_class)
+
+enum class St { Queued, Setup, Active, Finishing, Done };
+
+struct Req {
+    int64_t ticket = 0;
+    int64_t m = 0, n = 0, lda = 0, d = 0;
+    int32_t q = 0;
+    uint64_t seed = 0;
+    const double *A = nullptr, *b = nullptr;
+    double *x = nullptr;
+    int64_t footprint = 0;
+    St st = St::Queued;
+    int32_t rounds = 0;
+    double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+    ls_status result = LS_OK;
+    // device buffers (one block from the server's cache)
+    void *mem = nullptr;
+    size_t mem_bytes = 0;
+    double *R = nullptr, *RT = nullptr, *part = nullptr, *part_rr = nullptr, *c = nullptr, *rr = nullptr;
+    int32_t *status = nullptr;
+    int32_t P = 1;
+    int32_t *status_host = nullptr;    // pinned copy, written by the setup and by the last round
+    hipEvent_t ev = nullptr;           // end of setup, then end of the last round
+};
+
+}  // namespace
+
+struct ls_server {
+    int device = -1;
+    int64_t budget = 0;
+    int32_t max_active = 0;
+    int32_t zeta = 8;
+    Clock::time_point t0;
+    hipStream_t s_setup = nullptr, s_serve = nullptr;
+    // setup workspace (sketch and QR of one problem at a time)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // device slot table and work-group maps, and their pinned staging ring
+    ServeSlot *d_slots = nullptr;
+    int32_t *d_wgmap = nullptr;
+    size_t wgmap_cap = 0;
+    struct Stage {
+        ServeSlot *slots = nullptr;
+        int32_t *wgmap = nullptr;
+        hipEvent_t ev = nullptr;       // the copy out of this buffer has been consumed
+        bool used = false;
+    };
+    std::vector<Stage> stage;
+    size_t stage_next = 0;
+    std::vector<hipEvent_t> round_ev;  // ring of round-end events
+    std::deque<hipEvent_t> inflight;
+    size_t round_next = 0;
+    // device memory cache (blocks are reused, released at destroy)
+    std::vector<std::pair<size_t, void *>> free_blocks;
+    std::vector<void *> all_blocks;
+    std::vector<int32_t *> pinned_status;
+    // requests
+    std::mutex mu;
+    std::condition_variable cv_done, cv_work;
+    std::deque<Req *> queue;
+    std::map<int64_t, std::unique_ptr<Req>> reqs;
+    std::vector<Req *> setup, active, finishing;
+    bool table_dirty = true;
+    int64_t next_ticket = 1;
+    int64_t footprint_now = 0, footprint_peak = 0;
+    int64_t submitted = 0, completed = 0, rounds = 0;
+    int32_t admitted_live = 0;
+    bool stopping = false;
+    ls_status fatal = LS_OK;
+    std::string err;
+    std::thread thr;
+};
+
+namespace {
+
+double seconds_since(const ls_server *sv) { return std::chrono::duration<double>(Clock::now() - sv->t0).count(); }
+
+// Footprint of a resident problem (bytes): A and b, R, the embedding and the sketch while it is set
+// up -- 8 m n + 8 m + 8 n^2 + 4 zeta m + 8 d n.
+int64_t footprint(int64_t m, int64_t n, int64_t d, int32_t zeta)
+{
+    return 8 * m * n + 8 * m + 8 * n * n + 4 * (int64_t)zeta * m + 8 * d * n;
+}
+
+bool hip_ok(ls_server *sv, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return true;
+    if (sv->fatal == LS_OK) {
+        sv->fatal = LS_ERR_DEVICE;
+        sv->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return false;
+}
+
+void *take_block(ls_server *sv, size_t bytes)
+{
+    for (size_t i = 0; i < sv->free_blocks.size(); ++i)
+        if (sv->free_blocks[i].first >= bytes) {
+            void *p = sv->free_blocks[i].second;
+            sv->free_blocks.erase(sv->free_blocks.begin() + (long)i);
+            return p;
+        }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    sv->all_blocks.push_back(p);
+    return p;
+}
+
+void give_block(ls_server *sv, void *p, size_t bytes)
+{
+    if (p) sv->free_blocks.emplace_back(bytes, p);
+}
+
+// Per-problem device buffers: R, R^T, pass partials, c, ||r||^2, status word.
+bool alloc_req(ls_server *sv, Req *r)
+{
+    r->P = iter_partials(r->m, r->n);
+    Arena sizing;
+    auto carve = [&](Arena &ar) {
+        r->R = ar.take<double>((size_t)(r->n * r->n));
+        r->RT = ar.take<double>((size_t)(r->n * r->n));
+        r->part = ar.take<double>((size_t)r->P * (size_t)r->n);
+        r->part_rr = ar.take<double>((size_t)r->P);
+        r->c = ar.take<double>((size_t)r->n);
+        r->rr = ar.take<double>(1);
+        r->status = ar.take<int32_t>(1);
+    };
+    carve(sizing);
+    r->mem_bytes = sizing.off + 256;
+    r->mem = take_block(sv, r->mem_bytes);
+    if (!r->mem) return false;
+    Arena real;
+    real.base = static_cast<char *>(r->mem);
+    carve(real);
+    return true;
+}
+
+// Setup workspace large enough for the sketch and QR of one problem.
+bool ensure_setup_ws(ls_server *sv, size_t bytes)
+{
+    if (bytes <= sv->ws_bytes) return true;
+    if (!hip_ok(sv, hipStreamSynchronize(sv->s_setup), "setup stream synchronize")) return false;
+    if (sv->ws) (void)hipFree(sv->ws);
+    sv->ws = nullptr;
+    sv->ws_bytes = 0;
+    if (hipMalloc(&sv->ws, bytes + bytes / 4) != hipSuccess) {
+        (void)hipGetLastError();
+        sv->ws = nullptr;
+        return false;
+    }
+    sv->ws_bytes = bytes + bytes / 4;
+    return true;
+}
+
+// Enqueue sketch, QR, R, R^T and x_0 of one problem on the setup stream (as ls_solve does), then the
+// copy of its status word and the event the scheduler waits for.
+bool enqueue_setup(ls_server *sv, Req *r)
+{
+    hipStream_t s = sv->s_setup;
+    SketchBufs sb{};
+    QrBufs qb{};
+    auto carve = [&](Arena &ar) {
+        sketch_bufs(ar, r->m, r->d, sv->zeta, sb);
+        qr_bufs(ar, r->d, r->n, qb);
+    };
+    Arena sizing;
+    carve(sizing);
+    if (!ensure_setup_ws(sv, sizing.off + 256)) {
+        r->result = LS_ERR_ALLOC;
+        return false;
+    }
+    Arena real;
+    real.base = static_cast<char *>(sv->ws);
+    carve(real);
+    const int64_t n = r->n;
+    bool ok = hip_ok(sv, hipMemsetAsync(r->status, 0, sizeof(int32_t), s), "clear status") &&
+              hip_ok(sv, launch_sparse_sign(s, r->m, r->d, sv->zeta, r->seed, sb), "sparse-sign kernel") &&
+              hip_ok(sv, launch_csr(s, r->m, r->d, sv->zeta, sb), "CSR kernels") &&
+              hip_ok(sv, launch_gather(s, r->d, n, r->A, r->lda, r->b, sb.rowptr, sb.cols,
+                                       1.0 / std::sqrt((double)sv->zeta), qb.W, qb.ldw, qb.W + n, qb.ldw),
+                     "gather kernel") &&
+              // per-column panels: a cooperative grid barrier would have to share the device with
+              // the rounds running on the serve stream (both paths give the same bits)
+              hip_ok(sv, launch_qr(s, r->d, n, qb, r->status, true), "QR kernels") &&
+              hip_ok(sv, launch_extract_r(s, n, qb, r->R, n, r->status), "extract R") &&
+              hip_ok(sv, hipMemcpyAsync(r->RT, qb.RT, sizeof(double) * (size_t)(n * n), hipMemcpyDeviceToDevice, s), "copy R^T") &&
+              hip_ok(sv, launch_back_substitution(s, n, r->R, n, qb.RT, qb.qtb, r->x, r->status), "x0 solve") &&
+              hip_ok(sv, hipMemcpyAsync(r->status_host, r->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status") &&
+              hip_ok(sv, hipEventRecord(r->ev, s), "record setup event");
+    return ok;
+}
+
+ls_status status_of(int32_t st)
+{
+    if (st & ST_RANK) return LS_ERR_RANK;
+    if (st & ST_NONFINITE) return LS_ERR_NONFINITE;
+    if (st & ST_DIVERGED) return LS_ERR_DIVERGED;
+    if (st & ST_TIMEOUT) return LS_ERR_DEVICE;
+    return LS_OK;
+}
+
+// Called with the lock held: a request leaves the server.
+void finish(ls_server *sv, Req *r, ls_status result)
+{
+    r->result = result;
+    r->st = St::Done;
+    r->t_done = seconds_since(sv);
+    give_block(sv, r->mem, r->mem_bytes);
+    r->mem = nullptr;
+    sv->footprint_now -= r->footprint;
+    sv->admitted_live -= 1;
+    sv->completed += 1;
+    sv->cv_done.notify_all();
+}
+
+// Slot table and work-group maps of the current active set into the next staging buffer, copied to
+// the device on the serve stream.  Returns false on a device error.
+bool upload_table(ls_server *sv, int32_t class_wg[kClasses], int32_t class_off[kClasses], int32_t &red_wg,
+                  int32_t &red_off, int64_t &max_n)
+{
+    ls_server::Stage &stg = sv->stage[sv->stage_next];
+    sv->stage_next = (sv->stage_next + 1) % sv->stage.size();
+    if (stg.used && !hip_ok(sv, hipEventSynchronize(stg.ev), "staging reuse")) return false;
+    const int ns = (int)sv->active.size();
+    for (int k = 0; k < kClasses; ++k) class_wg[k] = 0;
+    max_n = 1;
+    // pass work-groups grouped by class, then the reduction work-groups
+    size_t off = 0;
+    for (int k = 0; k < kClasses; ++k) {
+        class_off[k] = (int32_t)off;
+        for (int i = 0; i < ns; ++i) {
+            Req *r = sv->active[i];
+            if (pass_class(r->n) != k) continue;
+            ServeSlot &sl = stg.slots[i];
+            sl.pass_base = class_wg[k];
+            for (int32_t p = 0; p < r->P; ++p) stg.wgmap[off++] = i;
+            class_wg[k] += r->P;
+        }
+    }
+    red_off = (int32_t)off;
+    red_wg = 0;
+    for (int i = 0; i < ns; ++i) {
+        Req *r = sv->active[i];
+        ServeSlot &sl = stg.slots[i];
+        sl.A = r->A;
+        sl.b = r->b;
+        sl.x = r->x;
+        sl.R = r->R;
+        sl.RT = r->RT;
+        sl.part = r->part;
+        sl.part_rr = r->part_rr;
+        sl.c = r->c;
+        sl.rr = r->rr;
+        sl.m = r->m;
+        sl.n = r->n;
+        sl.lda = r->lda;
+        sl.P = r->P;
+        sl.cls = pass_class(r->n);
+        sl.status = r->status;
+        sl.red_base = red_wg;
+        const int32_t blocks = (int32_t)((r->n + 63) / 64);
+        for (int32_t k2 = 0; k2 < blocks; ++k2) stg.wgmap[off++] = i;
+        red_wg += blocks;
+        max_n = std::max<int64_t>(max_n, r->n);
+    }
+    hipStream_t s = sv->s_serve;
+    if (!hip_ok(sv, hipMemcpyAsync(sv->d_slots, stg.slots, sizeof(ServeSlot) * (size_t)ns, hipMemcpyHostToDevice, s), "upload slots") ||
+        !hip_ok(sv, hipMemcpyAsync(sv->d_wgmap, stg.wgmap, sizeof(int32_t) * off, hipMemcpyHostToDevice, s), "upload map") ||
+        !hip_ok(sv, hipEventRecord(stg.ev, s), "record staging event"))
+        return false;
+    stg.used = true;
+    return true;
+}
+
+void scheduler(ls_server *sv)
+{
+    if (hipSetDevice(sv->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->fatal = LS_ERR_DEVICE;
+        sv->err = "scheduler: cannot select the device";
+        sv->cv_done.notify_all();
+        return;
+    }
+    int32_t class_wg[kClasses] = {0}, class_off[kClasses] = {0};
+    int32_t red_wg = 0, red_off = 0;
+    int64_t max_n = 1;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        bool progress = false;
+        if (sv->fatal != LS_OK) {             // fail everything still pending
+            for (auto &kv : sv->reqs)
+                if (kv.second->st != St::Done) finish(sv, kv.second.get(), sv->fatal);
+            sv->queue.clear();
+            sv->setup.clear();
+            sv->active.clear();
+            sv->finishing.clear();
+        }
+        // (1) admission: FIFO while the footprint budget and the slot table allow
+        while (!sv->queue.empty() && sv->admitted_live < sv->max_active &&
+               sv->footprint_now + sv->queue.front()->footprint <= sv->budget) {
+            Req *r = sv->queue.front();
+            sv->queue.pop_front();
+            r->t_admit = seconds_since(sv);
+            if (!alloc_req(sv, r)) {
+                r->result = LS_ERR_ALLOC;
+                r->st = St::Done;
+                r->t_done = r->t_admit;
+                sv->completed += 1;
+                sv->cv_done.notify_all();
+                continue;
+            }
+            sv->footprint_now += r->footprint;
+            sv->footprint_peak = std::max(sv->footprint_peak, sv->footprint_now);
+            sv->admitted_live += 1;
+            if (!enqueue_setup(sv, r)) {
+                finish(sv, r, r->result != LS_OK ? r->result : LS_ERR_DEVICE);
+                continue;
+            }
+            r->st = St::Setup;
+            sv->setup.push_back(r);
+            progress = true;
+        }
+        // (2) finished setups join the active set (or leave: error, or q = 0)
+        for (size_t i = 0; i < sv->setup.size();) {
+            Req *r = sv->setup[i];
+            const hipError_t e = hipEventQuery(r->ev);
+            if (e == hipErrorNotReady) { ++i; continue; }
+            sv->setup.erase(sv->setup.begin() + (long)i);
+            progress = true;
+            if (!hip_ok(sv, e, "setup event")) break;
+            const ls_status st = status_of(*r->status_host);
+            if (st != LS_OK || r->q == 0) {
+                finish(sv, r, st);
+                continue;
+            }
+            r->st = St::Active;
+            r->t_start = seconds_since(sv);
+            sv->active.push_back(r);
+            sv->table_dirty = true;
+        }
+        // (3) retire finished requests and rounds
+        while (!sv->inflight.empty() && hipEventQuery(sv->inflight.front()) == hipSuccess) {
+            sv->inflight.pop_front();
+            progress = true;
+        }
+        for (size_t i = 0; i < sv->finishing.size();) {
+            Req *r = sv->finishing[i];
+            const hipError_t e = hipEventQuery(r->ev);
+            if (e == hipErrorNotReady) { ++i; continue; }
+            sv->finishing.erase(sv->finishing.begin() + (long)i);
+            progress = true;
+            finish(sv, r, hip_ok(sv, e, "round event") ? status_of(*r->status_host) : LS_ERR_DEVICE);
+        }
+        // (4) one more round of every active problem, if fewer than kRoundsInFlight are queued
+        if (!sv->active.empty() && (int)sv->inflight.size() < kRoundsInFlight && sv->fatal == LS_OK) {
+            if (sv->table_dirty) {
+                if (!upload_table(sv, class_wg, class_off, red_wg, red_off, max_n)) continue;
+                sv->table_dirty = false;
+            }
+            hipStream_t s = sv->s_serve;
+            bool ok = true;
+            for (int k = 0; k < kClasses && ok; ++k)
+                ok = hip_ok(sv, launch_served_pass(s, k, class_wg[k], sv->d_slots, sv->d_wgmap + class_off[k]), "served pass");
+            ok = ok && hip_ok(sv, launch_served_reduce(s, red_wg, sv->d_slots, sv->d_wgmap + red_off), "served reduce") &&
+                 hip_ok(sv, launch_served_solve(s, (int)sv->active.size(), max_n, sv->d_slots), "served solve");
+            if (!ok) continue;
+            sv->rounds += 1;
+            for (size_t i = 0; i < sv->active.size();) {
+                Req *r = sv->active[i];
+                if (++r->rounds < r->q) { ++i; continue; }
+                // last round of this problem: its status word, then its completion event
+                ok = hip_ok(sv, hipMemcpyAsync(r->status_host, r->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status") &&
+                     hip_ok(sv, hipEventRecord(r->ev, s), "record last round");
+                r->st = St::Finishing;
+                sv->finishing.push_back(r);
+                sv->active.erase(sv->active.begin() + (long)i);
+                sv->table_dirty = true;
+            }
+            hipEvent_t ev = sv->round_ev[sv->round_next];
+            sv->round_next = (sv->round_next + 1) % sv->round_ev.size();
+            if (hip_ok(sv, hipEventRecord(ev, s), "record round")) sv->inflight.push_back(ev);
+            progress = true;
+        }
+        const bool idle = sv->queue.empty() && sv->setup.empty() && sv->active.empty() && sv->finishing.empty();
+        if (idle && sv->stopping) break;
+        if (!progress) {
+            // nothing to do right now: wait for a submission, or poll the device again shortly
+            if (idle) sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
+            else {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            }
+        }
+    }
+    // drain the device before the streams and buffers go away
+    lk.unlock();
+    (void)hipStreamSynchronize(sv->s_serve);
+    (void)hipStreamSynchronize(sv->s_setup);
+}
+
+ls_status check_solve_args(ls_server *sv, int64_t m, int64_t n, const double *A, int64_t lda,
+                           const double *b, int64_t d, int32_t q, const double *x)
+{
+    auto fail = [&](ls_status st, const char *msg) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->err = msg;
+        return st;
+    };
+    if (n < 1) return fail(LS_ERR_ARG, "n must be >= 1");
+    if (n > LS_MAX_N) return fail(LS_ERR_UNSUPPORTED, "n exceeds LS_MAX_N");
+    if (m < n) return fail(LS_ERR_ARG, "m must be >= n");
+    if (d < n) return fail(LS_ERR_ARG, "d must be >= n");
+    if (d >= (int64_t(1) << 31)) return fail(LS_ERR_ARG, "d must be < 2^31");
+    if (q < 0) return fail(LS_ERR_ARG, "q must be >= 0");
+    if (sv->zeta > d) return fail(LS_ERR_ARG, "zeta must be <= d");
+    if (m * (int64_t)sv->zeta >= (int64_t(1) << 31)) return fail(LS_ERR_UNSUPPORTED, "m*zeta must be < 2^31");
+    auto aligned8 = [](const void *p) { return p && (reinterpret_cast<uintptr_t>(p) % 8) == 0; };
+    if (!aligned8(A) || !aligned8(b) || !aligned8(x)) return fail(LS_ERR_ARG, "A, b and x must be non-NULL and 8-byte aligned");
+    if (lda < n) return fail(LS_ERR_ARG, "leading dimension of A < n");
+    return LS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ls_status ls_server_create(int device, int64_t budget_bytes, int32_t max_active, ls_server **out)
+{
+    if (!out) return LS_ERR_ARG;
+    *out = nullptr;
+    if (budget_bytes <= 0 || max_active < 1 || max_active > 4096) return LS_ERR_ARG;
+    auto sv = std::unique_ptr<ls_server>(new (std::nothrow) ls_server);
+    if (!sv) return LS_ERR_ALLOC;
+    sv->budget = budget_bytes;
+    sv->max_active = max_active;
+    sv->t0 = Clock::now();
+    if (device == -1) {                    // host-only: argument checks, no device work
+        *out = sv.release();
+        return LS_OK;
+    }
+    int count = 0;
+    if (device < 0 || hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        (void)hipGetLastError();
+        return LS_ERR_DEVICE;
+    }
+    sv->device = device;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    bool ok = hipSetDevice(device) == hipSuccess;
+    // map capacity: pass work-groups of max_active problems (at most 2048 each) plus their
+    // reduction blocks (at most LS_MAX_N / 64 each)
+    sv->wgmap_cap = (size_t)max_active * (2048 + LS_MAX_N / 64);
+    ok = ok && hipStreamCreateWithFlags(&sv->s_setup, hipStreamNonBlocking) == hipSuccess &&
+         hipStreamCreateWithFlags(&sv->s_serve, hipStreamNonBlocking) == hipSuccess &&
+         hipMalloc(&sv->d_slots, sizeof(ServeSlot) * (size_t)max_active) == hipSuccess &&
+         hipMalloc(&sv->d_wgmap, sizeof(int32_t) * sv->wgmap_cap) == hipSuccess;
+    sv->stage.resize(3);
+    for (auto &st : sv->stage)
+        ok = ok && hipHostMalloc(&st.slots, sizeof(ServeSlot) * (size_t)max_active, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&st.wgmap, sizeof(int32_t) * sv->wgmap_cap, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) == hipSuccess;
+    sv->round_ev.resize(kRoundsInFlight + 2);
+    for (auto &e : sv->round_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (!ok) {
+        (void)hipGetLastError();
+        ls_server_destroy(sv.release());
+        return LS_ERR_DEVICE;
+    }
+    sv->thr = std::thread(scheduler, sv.get());
+    *out = sv.release();
+    return LS_OK;
+}
+
+void ls_server_destroy(ls_server *sv)
+{
+    if (!sv) return;
+    if (sv->thr.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stopping = true;
+        }
+        sv->cv_work.notify_all();
+        sv->thr.join();
+    }
+    if (sv->device >= 0) {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(sv->device);
+        if (sv->s_serve) (void)hipStreamSynchronize(sv->s_serve);
+        if (sv->s_setup) (void)hipStreamSynchronize(sv->s_setup);
+        for (auto &kv : sv->reqs) {
+            if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+        }
+        for (int32_t *p : sv->pinned_status) (void)hipHostFree(p);
+        for (void *p : sv->all_blocks) (void)hipFree(p);
+        for (auto &st : sv->stage) {
+            if (st.slots) (void)hipHostFree(st.slots);
+            if (st.wgmap) (void)hipHostFree(st.wgmap);
+            if (st.ev) (void)hipEventDestroy(st.ev);
+        }
+        for (auto &e : sv->round_ev) if (e) (void)hipEventDestroy(e);
+        if (sv->ws) (void)hipFree(sv->ws);
+        if (sv->d_slots) (void)hipFree(sv->d_slots);
+        if (sv->d_wgmap) (void)hipFree(sv->d_wgmap);
+        if (sv->s_setup) (void)hipStreamDestroy(sv->s_setup);
+        if (sv->s_serve) (void)hipStreamDestroy(sv->s_serve);
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    delete sv;
+}
+
+ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A, int64_t lda,
+                           const double *b, int64_t d, int32_t q, uint64_t seed, double *x,
+                           int64_t *ticket)
+{
+    if (!sv || !ticket) return LS_ERR_ARG;
+    {
+        const ls_status st = check_solve_args(sv, m, n, A, lda, b, d, q, x);
+        if (st != LS_OK) return st;
+    }
+    const int64_t fp = footprint(m, n, d, sv->zeta);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (fp > sv->budget) {
+        sv->err = "the problem's footprint exceeds the server's HBM budget";
+        return LS_ERR_ALLOC;
+    }
+    if (sv->device < 0) {
+        sv->err = "host-only server: no device work";
+        return LS_ERR_DEVICE;
+    }
+    if (sv->fatal != LS_OK) return sv->fatal;
+    auto r = std::unique_ptr<Req>(new (std::nothrow) Req);
+    if (!r) return LS_ERR_ALLOC;
+    int32_t *pin = nullptr;
+    if (hipHostMalloc(&pin, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (pin) (void)hipHostFree(pin);
+        sv->err = "cannot allocate the request's pinned status word or event";
+        return LS_ERR_DEVICE;
+    }
+    sv->pinned_status.push_back(pin);
+    *pin = 0;
+    r->status_host = pin;
+    r->ticket = sv->next_ticket++;
+    r->m = m;
+    r->n = n;
+    r->lda = lda;
+    r->d = d;
+    r->q = q;
+    r->seed = seed;
+    r->A = A;
+    r->b = b;
+    r->x = x;
+    r->footprint = fp;
+    r->t_submit = seconds_since(sv);
+    *ticket = r->ticket;
+    sv->queue.push_back(r.get());
+    sv->reqs[r->ticket] = std::move(r);
+    sv->submitted += 1;
+    lk.unlock();
+    sv->cv_work.notify_all();
+    return LS_OK;
+}
+
+ls_status ls_server_wait(ls_server *sv, int64_t ticket, double timeout_s, ls_status *result)
+{
+    if (!sv) return LS_ERR_ARG;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) {
+        sv->err = "unknown ticket";
+        return LS_ERR_ARG;
+    }
+    Req *r = it->second.get();
+    auto done = [&] { return r->st == St::Done; };
+    if (timeout_s < 0) sv->cv_done.wait(lk, done);
+    else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) return LS_ERR_TIMEOUT;
+    if (result) *result = r->result;
+    return LS_OK;
+}
+
+ls_status ls_server_request_info(ls_server *sv, int64_t ticket, double *times)
+{
+    if (!sv || !times) return LS_ERR_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return LS_ERR_ARG;
+    const Req *r = it->second.get();
+    times[0] = r->t_submit;
+    times[1] = r->t_admit;
+    times[2] = r->t_start;
+    times[3] = r->t_done;
+    return LS_OK;
+}
+
+ls_status ls_server_stats(ls_server *sv, int64_t *stats)
+{
+    if (!sv || !stats) return LS_ERR_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    stats[0] = sv->submitted;
+    stats[1] = sv->completed;
+    stats[2] = (int64_t)sv->queue.size();
+    stats[3] = sv->admitted_live;
+    stats[4] = sv->footprint_now;
+    stats[5] = sv->footprint_peak;
+    stats[6] = sv->rounds;
+    return LS_OK;
+}
+
+const char *ls_server_last_error(ls_server *sv)
+{
+    if (!sv) return "null server";
+    std::lock_guard<std::mutex> lk(sv->mu);
+    return sv->err.c_str();
+}
+
+}  // extern "C"

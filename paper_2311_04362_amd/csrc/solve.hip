@@ -573,6 +573,32 @@ k_solve(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ R
     if (st_state && threadIdx.x == 0) st_state[1] += 1;
 }
 
+// Served rounds: d = R^{-1} (R^{-T} c) and x += d for every resident problem, one work-group each,
+// with the arithmetic of k_solve (FP64, plain update) on that problem alone.
+template <int kSB>
+__global__ void __launch_bounds__(kSolveThreads)
+k_solve_served(const ServeSlot *__restrict__ slots)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *s = reinterpret_cast<double *>(smem);
+    __shared__ SubstLds<double, kSB> L;
+    __shared__ double red[kSolveThreads / 64];
+    const ServeSlot &sl = slots[blockIdx.x];
+    const int64_t n = sl.n;
+    (void)load_rhs<double>(n, sl.c, s, red);
+    zero_pad<double, kSB>(n, s);
+    __syncthreads();
+    fwd_subst<double, kSB, kSolveThreads>(n, sl.R, n, s, L);
+    back_subst<double, kSB, kSolveThreads>(n, sl.R, n, sl.RT, s, L);
+    bool bad = false;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const double xn = sl.x[j] + s[j];
+        sl.x[j] = xn;
+        bad |= !isfinite(xn);
+    }
+    if (bad) atomicOr(sl.status, ST_NONFINITE);
+}
+
 // Section 3.3 estimators, one work-group, in the arithmetic of the factor (T).
 //   normest: v = g/||g|| with g_i uniform on [-1, 1) (53 high bits of SplitMix64 output i of the
 //            stream `seed`); ceil(ln n) times: w = R v, est = ||w||, v = R^T w / ||R^T w||.
@@ -842,6 +868,14 @@ hipError_t launch_estimators(hipStream_t s, int64_t n, const float *R, int64_t l
                              const float *RT, uint64_t seed, float *work, double *scal)
 {
     return estimators_impl(s, n, R, ldr, RT, seed, work, scal);
+}
+
+hipError_t launch_served_solve(hipStream_t s, int nslots, int64_t max_n, const ServeSlot *slots)
+{
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve_served<kSolveBlock>, dim3(nslots), dim3(kSolveThreads),
+                       (size_t)padded<kSolveBlock>(max_n) * sizeof(double), s, slots);
+    return hipGetLastError();
 }
 
 hipError_t launch_stop_init(hipStream_t s, int32_t *state)

@@ -15,9 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libls.so")
 
 LS_OK, LS_ERR_ARG, LS_ERR_ALLOC, LS_ERR_DEVICE, LS_ERR_RANK, LS_ERR_NONFINITE, \
-    LS_ERR_DIVERGED, LS_ERR_UNSUPPORTED = range(8)
+    LS_ERR_DIVERGED, LS_ERR_UNSUPPORTED, LS_ERR_TIMEOUT = range(9)
 STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_RANK",
-                "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED"]
+                "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED", "LS_ERR_TIMEOUT"]
 OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL, \
     OPT_STOP, OPT_GAMMA, OPT_RHO = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 NORMEST_SEED_OFFSET = 0x632BE59BD9B4E019
@@ -26,7 +26,9 @@ PRECISION_FP64, PRECISION_MIXED, PRECISION_FELL_BACK_COND, PRECISION_FELL_BACK_G
 EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_option",
            "ls_get_option", "ls_sketch_embedding", "ls_sketch_csr", "ls_sketch", "ls_qr_sketch",
            "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile",
-           "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32"]
+           "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32",
+           "ls_server_create", "ls_server_destroy", "ls_server_submit", "ls_server_wait",
+           "ls_server_request_info", "ls_server_stats", "ls_server_last_error"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -73,6 +75,14 @@ def load():
         "ls_sketch_f32": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _u64, _vp, _i64, _vp], ctypes.c_int),
         "ls_qr_sketch_f32": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp], ctypes.c_int),
         "ls_precond_solve_f32": ([_vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
+        "ls_server_create": ([ctypes.c_int, _i64, _i32, ctypes.POINTER(_vp)], ctypes.c_int),
+        "ls_server_destroy": ([_vp], None),
+        "ls_server_submit": ([_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _u64, _vp,
+                              ctypes.POINTER(_i64)], ctypes.c_int),
+        "ls_server_wait": ([_vp, _i64, _f64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "ls_server_request_info": ([_vp, _i64, ctypes.POINTER(_f64)], ctypes.c_int),
+        "ls_server_stats": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
+        "ls_server_last_error": ([_vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -253,6 +263,70 @@ class Context:
         ms, cnt = _f64(), _i64()
         self._check(self._L.ls_profile(self.h, ctypes.byref(ms), ctypes.byref(cnt), int(reset)), "ls_profile")
         return ms.value, cnt.value
+
+
+class Server:
+    """A served stream of FP64 solves on one GPU (ls_server_*).  submit() returns a ticket at once;
+    the tensors stay referenced here until wait() has seen the request finish."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 64 << 30, max_active: int = 1024):
+        self._L = load()
+        h = _vp()
+        st = self._L.ls_server_create(device, budget_bytes, max_active, ctypes.byref(h))
+        if st != LS_OK:
+            raise LSError(st, "ls_server_create", f"device {device}")
+        self.h = h
+        self.device = device
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.ls_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, where: str):
+        if st != LS_OK:
+            raise LSError(st, where, self._L.ls_server_last_error(self.h).decode())
+
+    def submit(self, A: torch.Tensor, b: torch.Tensor, d: int, q: int, seed: int,
+               x: torch.Tensor | None = None):
+        m, n, lda = _mat(A, "A")
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=A.device)
+        # the server's streams run apart from torch's: the inputs must be complete on the device
+        torch.cuda.current_stream().synchronize()
+        t = _i64()
+        self._check(self._L.ls_server_submit(self.h, m, n, _ptr(A), lda, _ptr(_vec(b, "b")), d, q,
+                                             seed, _ptr(_vec(x, "x")), ctypes.byref(t)),
+                    "ls_server_submit")
+        self._keep[t.value] = (A, b, x)
+        return t.value, x
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> int:
+        """Waits for the request; returns its status (LS_OK or that problem's deferred error)."""
+        res = ctypes.c_int(0)
+        self._check(self._L.ls_server_wait(self.h, ticket, timeout, ctypes.byref(res)), "ls_server_wait")
+        self._keep.pop(ticket, None)
+        return res.value
+
+    def times(self, ticket: int):
+        """(submitted, admitted, first round, finished), seconds since the server was created."""
+        t = (_f64 * 4)()
+        self._check(self._L.ls_server_request_info(self.h, ticket, t), "ls_server_request_info")
+        return tuple(t)
+
+    def stats(self):
+        s = (_i64 * 7)()
+        self._check(self._L.ls_server_stats(self.h, s), "ls_server_stats")
+        keys = ["submitted", "finished", "queued", "admitted", "footprint", "footprint_peak", "rounds"]
+        return dict(zip(keys, list(s)))
 
 
 def limits():

@@ -192,3 +192,30 @@ def test_stop_options(L, hctx):
     pr = ctypes.c_int32(-1)
     assert L.ls_solve_info(hctx, ctypes.byref(d), ctypes.byref(q), None, None, ctypes.byref(pr)) == ls.LS_OK
     assert pr.value == ls.PRECISION_FP64
+
+
+def test_server_argument_errors(L):
+    h = ctypes.c_void_p()
+    assert L.ls_server_create(-1, 0, 16, ctypes.byref(h)) == ls.LS_ERR_ARG        # no budget
+    assert L.ls_server_create(-1, 1 << 30, 0, ctypes.byref(h)) == ls.LS_ERR_ARG    # no slots
+    assert L.ls_server_create(-1, 1 << 30, 16, ctypes.byref(h)) == ls.LS_OK
+    t = ctypes.c_int64()
+    try:
+        def sub(m=100, n=10, A=P, lda=10, b=P, d=200, q=5, x=P):
+            return L.ls_server_submit(h, m, n, A, lda, b, d, q, 0, x, ctypes.byref(t))
+        assert sub() == ls.LS_ERR_DEVICE                  # valid: stops at "no device"
+        assert sub(m=9) == ls.LS_ERR_ARG
+        assert sub(d=9) == ls.LS_ERR_ARG
+        assert sub(q=-1) == ls.LS_ERR_ARG
+        assert sub(lda=9) == ls.LS_ERR_ARG
+        assert sub(A=NUL) == ls.LS_ERR_ARG
+        assert sub(x=ctypes.c_void_p(0x10004)) == ls.LS_ERR_ARG
+        assert sub(n=4096, lda=4096, m=10000, d=100000) == ls.LS_ERR_UNSUPPORTED
+        assert sub(m=1 << 26, n=2000, lda=2000, d=40000) == ls.LS_ERR_ALLOC          # over budget
+        assert b"budget" in L.ls_server_last_error(h)
+        res = ctypes.c_int()
+        assert L.ls_server_wait(h, 12345, 0.0, ctypes.byref(res)) == ls.LS_ERR_ARG   # unknown ticket
+        st = (ctypes.c_int64 * 7)()
+        assert L.ls_server_stats(h, st) == ls.LS_OK and st[0] == 0
+    finally:
+        L.ls_server_destroy(h)
