@@ -16,6 +16,10 @@ Other workloads (one JSON line each):
                                   error: both stop at their accuracy floor) and at q = 40
     --workload ls_large_m4e6_n2000  m = 4,000,000, n = 2000 (A is 64 GB), d = 40,000, q = 40, FP64
                                   and mixed
+    --workload served_512         512 FP64 problems (m log-uniform on [2e4, 2e5], n in {32, 64, 128,
+                                  256}, kappa log-uniform on [1e2, 1e12], ||r|| = 1e-6, d = 20 n, q = 40)
+                                  through the served stream, arriving Poisson at 200/s and all at
+                                  once (saturation), against ls_solve one request at a time
 """
 from __future__ import annotations
 
@@ -38,6 +42,8 @@ WORKLOADS = {
     "mixed_m1e6_n1000": dict(m=1_000_000, n=1000, d=20_000, zeta=8, q=40, kappas=(1e2, 1e6, 1e12),
                              betas=(1e-12, 1e-3, 1.0), qmax=200),
     "ls_large_m4e6_n2000": dict(m=4_000_000, n=2000, d=40_000, zeta=8, q=40, kappa=1e10, beta=1e-6),
+    "served_512": dict(count=512, rate=200.0, m_lo=20_000, m_hi=200_000, ns=(32, 64, 128, 256),
+                       kappa_lo=1e2, kappa_hi=1e12, beta=1e-6, q=40, zeta=8),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_ls_fp64_m2e6_n500_traffic.json")
 
@@ -215,6 +221,133 @@ def bench_large(args, w):
     ctx.close()
 
 
+def served_problems(w, seed=7):
+    """The request stream: shapes, conditioning and Poisson arrival times, seeded."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(w["count"]):
+        m = int(math.floor(math.exp(rng.uniform(math.log(w["m_lo"]), math.log(w["m_hi"])))))
+        n = int(rng.choice(w["ns"]))
+        kappa = math.exp(rng.uniform(math.log(w["kappa_lo"]), math.log(w["kappa_hi"])))
+        t += rng.exponential(1.0 / w["rate"])
+        out.append(dict(m=m, n=n, kappa=kappa, d=20 * n, arrival=t, seed=1000 + i))
+    return out
+
+
+def pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(math.ceil(q / 100.0 * len(v))) - 1)]
+
+
+def bench_served(args, w):
+    """Served stream against ls_solve one request at a time, Poisson arrivals and saturation."""
+    import threading
+
+    import torch
+
+    from paper_2311_04362_amd import ls
+    from synth import ProblemSpec, make_problem_gpu
+
+    reqs = served_problems(w)
+    t_gen = time.perf_counter()
+    probs = []
+    for r in reqs:
+        spec = ProblemSpec(m=r["m"], n=r["n"], kappa=r["kappa"], beta=w["beta"], d=r["d"], q=w["q"],
+                           zeta=w["zeta"], seed=r["seed"])
+        p = make_problem_gpu(spec)
+        probs.append((spec, p.A[:, :r["n"]], p.b, p.x_true))
+    torch.cuda.synchronize()
+    resident = sum(8 * r["m"] * r["n"] + 8 * r["m"] for r in reqs)
+    print(f"[bench] generated {len(reqs)} problems ({resident / 1e9:.1f} GB of A and b) in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    q = w["q"]
+
+    def served(poisson: bool):
+        srv = ls.Server(0, budget_bytes=200 << 30, max_active=len(reqs))
+        xs = [torch.empty(r["n"], dtype=torch.float64, device="cuda") for r in reqs]
+        # warm-up: one small request compiles nothing but touches every code path once
+        spec, A, b, _ = probs[0]
+        t, _ = srv.submit(A, b, spec.d, q, spec.sketch_seed)
+        srv.wait(t)
+        tickets = [None] * len(reqs)
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i, (spec, A, b, _) in enumerate(probs):
+                if poisson:
+                    delay = t_start + reqs[i]["arrival"] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets[i] = srv.submit(A, b, spec.d, q, spec.sketch_seed, xs[i])[0]
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        status = [srv.wait(t) for t in tickets]
+        t_end = time.perf_counter()
+        lat = []
+        for t in tickets:
+            t0, _, _, t3 = srv.times(t)
+            lat.append(t3 - t0)
+        stats = srv.stats()
+        srv.close()
+        return {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
+                "rounds": stats["rounds"], "failed": sum(1 for s_ in status if s_ != ls.LS_OK),
+                "footprint_peak_GB": stats["footprint_peak"] / 1e9}, xs
+
+    def baseline(poisson: bool):
+        ctx = ls.Context(0)
+        ctx.set_option(ls.OPT_ZETA, w["zeta"])
+        xs = []
+        spec, A, b, _ = probs[0]
+        ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+        ctx.solve(A, b, spec.d, q)
+        lat = []
+        t_start = time.perf_counter()
+        for i, (spec, A, b, _) in enumerate(probs):
+            arrival = t_start + (reqs[i]["arrival"] if poisson else 0.0)
+            delay = arrival - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+            xs.append(ctx.solve(A, b, spec.d, q))      # waits for the result
+            lat.append(time.perf_counter() - arrival)
+        t_end = time.perf_counter()
+        ctx.close()
+        return {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99)}, xs
+
+    out = {}
+    out["served_saturation"], xs_sat = served(False)
+    print(f"[bench] served saturation: {out['served_saturation']}", file=sys.stderr, flush=True)
+    out["served_poisson"], _ = served(True)
+    print(f"[bench] served poisson: {out['served_poisson']}", file=sys.stderr, flush=True)
+    out["ls_solve_saturation"], xs_base = baseline(False)
+    print(f"[bench] ls_solve saturation: {out['ls_solve_saturation']}", file=sys.stderr, flush=True)
+    out["ls_solve_poisson"], _ = baseline(True)
+    print(f"[bench] ls_solve poisson: {out['ls_solve_poisson']}", file=sys.stderr, flush=True)
+    same = all(torch.equal(a, b_) for a, b_ in zip(xs_sat, xs_base))
+    fe = [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs_sat, probs)]
+    rec = {
+        "metric": "served solves/s (saturation) with p50/p99 latency under Poisson arrivals",
+        "value": out["served_saturation"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": 1e3 * out["served_saturation"]["seconds"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "requests": len(reqs), "rate_per_s": w["rate"],
+                   "m": [w["m_lo"], w["m_hi"]], "n": list(w["ns"]), "kappa": [w["kappa_lo"], w["kappa_hi"]],
+                   "residual_norm": w["beta"], "d": "20n", "q": q, "zeta": w["zeta"],
+                   "resident_GB": resident / 1e9},
+        "speedup_saturation_vs_ls_solve": out["served_saturation"]["solves_per_s"] / out["ls_solve_saturation"]["solves_per_s"],
+        "bitwise_equal_to_ls_solve": same,
+        "forward_error_max": max(fe),
+        **out,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +369,8 @@ def main():
         return bench_mixed(args, w)
     if args.workload.startswith("ls_large_"):
         return bench_large(args, w)
+    if args.workload.startswith("served_"):
+        return bench_served(args, w)
 
     import torch
 

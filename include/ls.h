@@ -200,7 +200,7 @@ ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float
  * and returns, for each, the same bits ls_solve returns for it alone.  Problems are admitted first
  * in, first out while the sum of the footprints 8mn + 8m + 8n^2 + 4 zeta m + 8dn of the admitted
  * problems stays within `budget_bytes` and at most `max_active` are admitted; the sketch, QR and
- * start of each are computed on a setup stream, one problem after another, and then every
+ * start of each are computed on one of four setup streams (four problems at a time), then every
  * admitted problem takes one refinement step per round on a serve stream (one batched launch per
  * kernel for all of them: continuous batching -- problems join and leave between rounds).  A
  * scheduler thread owned by the server does all device work.  A, b and x are device pointers owned

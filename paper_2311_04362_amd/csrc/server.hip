@@ -1,6 +1,6 @@
 // Served stream of least-squares solves: many independent problems min ||b - A x|| resident on one
-// GPU, admitted by HBM footprint, set up (sketch, QR, sketch-and-solve start) one after another on
-// a setup stream, and iterated together in rounds on a serve stream.  A round is one refinement
+// GPU, admitted by HBM footprint, set up (sketch, QR, sketch-and-solve start) on a few setup lanes
+// (a stream and a workspace each), and iterated together in rounds on a serve stream.  A round is one refinement
 // step (Algorithm 2 loop body) of every resident problem: one batched pass launch per pass class,
 // one batched reduction and one batched solve + update (pass.hip, solve.hip).  Problems join at the
 // next round after their setup and leave after their q-th (continuous batching), so the launch cost
@@ -26,7 +26,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kRoundsInFlight = 2;     // rounds enqueued ahead of the host
+constexpr int kRoundsInFlight = 3;     // rounds enqueued ahead of the host
+constexpr int kSetupLanes = 4;         // setups in flight at once (each on its own stream)
 constexpr int kClasses = 9;            // pass classes (pass_class)
 
 enum class St { Queued, Setup, Active, Finishing, Done };
@@ -51,6 +52,7 @@ struct Req {
     int32_t P = 1;
     int32_t *status_host = nullptr;    // pinned copy, written by the setup and by the last round
     hipEvent_t ev = nullptr;           // end of setup, then end of the last round
+    int lane = -1;                     // setup lane while in setup
 };
 
 }  // namespace
@@ -61,10 +63,15 @@ struct ls_server {
     int32_t max_active = 0;
     int32_t zeta = 8;
     Clock::time_point t0;
-    hipStream_t s_setup = nullptr, s_serve = nullptr;
-    // setup workspace (sketch and QR of one problem at a time)
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
+    hipStream_t s_serve = nullptr;
+    // setup lanes: a stream and a workspace (sketch and QR of one problem at a time) each
+    struct Lane {
+        hipStream_t s = nullptr;
+        void *ws = nullptr;
+        size_t ws_bytes = 0;
+        bool busy = false;
+    };
+    std::vector<Lane> lanes;
     // device slot table and work-group maps, and their pinned staging ring
     ServeSlot *d_slots = nullptr;
     int32_t *d_wgmap = nullptr;
@@ -168,28 +175,36 @@ bool alloc_req(ls_server *sv, Req *r)
     return true;
 }
 
-// Setup workspace large enough for the sketch and QR of one problem.
-bool ensure_setup_ws(ls_server *sv, size_t bytes)
+// A lane's workspace large enough for the sketch and QR of one problem (the lane is idle here).
+bool ensure_setup_ws(ls_server *sv, ls_server::Lane &ln, size_t bytes)
 {
-    if (bytes <= sv->ws_bytes) return true;
-    if (!hip_ok(sv, hipStreamSynchronize(sv->s_setup), "setup stream synchronize")) return false;
-    if (sv->ws) (void)hipFree(sv->ws);
-    sv->ws = nullptr;
-    sv->ws_bytes = 0;
-    if (hipMalloc(&sv->ws, bytes + bytes / 4) != hipSuccess) {
+    if (bytes <= ln.ws_bytes) return true;
+    if (!hip_ok(sv, hipStreamSynchronize(ln.s), "setup stream synchronize")) return false;
+    if (ln.ws) (void)hipFree(ln.ws);
+    ln.ws = nullptr;
+    ln.ws_bytes = 0;
+    if (hipMalloc(&ln.ws, bytes + bytes / 4) != hipSuccess) {
         (void)hipGetLastError();
-        sv->ws = nullptr;
+        ln.ws = nullptr;
         return false;
     }
-    sv->ws_bytes = bytes + bytes / 4;
+    ln.ws_bytes = bytes + bytes / 4;
     return true;
 }
 
-// Enqueue sketch, QR, R, R^T and x_0 of one problem on the setup stream (as ls_solve does), then the
-// copy of its status word and the event the scheduler waits for.
-bool enqueue_setup(ls_server *sv, Req *r)
+int free_lane(const ls_server *sv)
 {
-    hipStream_t s = sv->s_setup;
+    for (size_t i = 0; i < sv->lanes.size(); ++i)
+        if (!sv->lanes[i].busy) return (int)i;
+    return -1;
+}
+
+// Enqueue sketch, QR, R, R^T and x_0 of one problem on a free setup lane (as ls_solve does), then the
+// copy of its status word and the event the scheduler waits for.
+bool enqueue_setup(ls_server *sv, Req *r, int lane)
+{
+    ls_server::Lane &ln = sv->lanes[lane];
+    hipStream_t s = ln.s;
     SketchBufs sb{};
     QrBufs qb{};
     auto carve = [&](Arena &ar) {
@@ -198,12 +213,12 @@ bool enqueue_setup(ls_server *sv, Req *r)
     };
     Arena sizing;
     carve(sizing);
-    if (!ensure_setup_ws(sv, sizing.off + 256)) {
+    if (!ensure_setup_ws(sv, ln, sizing.off + 256)) {
         r->result = LS_ERR_ALLOC;
         return false;
     }
     Arena real;
-    real.base = static_cast<char *>(sv->ws);
+    real.base = static_cast<char *>(ln.ws);
     carve(real);
     const int64_t n = r->n;
     bool ok = hip_ok(sv, hipMemsetAsync(r->status, 0, sizeof(int32_t), s), "clear status") &&
@@ -328,8 +343,8 @@ void scheduler(ls_server *sv)
             sv->active.clear();
             sv->finishing.clear();
         }
-        // (1) admission: FIFO while the footprint budget and the slot table allow
-        while (!sv->queue.empty() && sv->admitted_live < sv->max_active &&
+        // (1) admission: FIFO while the footprint budget, the slot table and a setup lane allow
+        while (!sv->queue.empty() && sv->admitted_live < sv->max_active && free_lane(sv) >= 0 &&
                sv->footprint_now + sv->queue.front()->footprint <= sv->budget) {
             Req *r = sv->queue.front();
             sv->queue.pop_front();
@@ -345,10 +360,13 @@ void scheduler(ls_server *sv)
             sv->footprint_now += r->footprint;
             sv->footprint_peak = std::max(sv->footprint_peak, sv->footprint_now);
             sv->admitted_live += 1;
-            if (!enqueue_setup(sv, r)) {
+            const int lane = free_lane(sv);
+            if (!enqueue_setup(sv, r, lane)) {
                 finish(sv, r, r->result != LS_OK ? r->result : LS_ERR_DEVICE);
                 continue;
             }
+            sv->lanes[lane].busy = true;
+            r->lane = lane;
             r->st = St::Setup;
             sv->setup.push_back(r);
             progress = true;
@@ -359,6 +377,8 @@ void scheduler(ls_server *sv)
             const hipError_t e = hipEventQuery(r->ev);
             if (e == hipErrorNotReady) { ++i; continue; }
             sv->setup.erase(sv->setup.begin() + (long)i);
+            sv->lanes[r->lane].busy = false;
+            r->lane = -1;
             progress = true;
             if (!hip_ok(sv, e, "setup event")) break;
             const ls_status st = status_of(*r->status_host);
@@ -417,11 +437,15 @@ void scheduler(ls_server *sv)
         const bool idle = sv->queue.empty() && sv->setup.empty() && sv->active.empty() && sv->finishing.empty();
         if (idle && sv->stopping) break;
         if (!progress) {
-            // nothing to do right now: wait for a submission, or poll the device again shortly
+            // nothing to do right now: wait for a submission; while rounds run, poll the device
+            // again at once (a sleep would add its wake-up delay to every round); while only setups
+            // run, poll every few microseconds
             if (idle) sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
             else {
+                const bool rounds_running = !sv->active.empty() || !sv->finishing.empty();
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                if (rounds_running) std::this_thread::yield();
+                else std::this_thread::sleep_for(std::chrono::microseconds(5));
                 lk.lock();
             }
         }
@@ -429,7 +453,7 @@ void scheduler(ls_server *sv)
     // drain the device before the streams and buffers go away
     lk.unlock();
     (void)hipStreamSynchronize(sv->s_serve);
-    (void)hipStreamSynchronize(sv->s_setup);
+    for (auto &ln : sv->lanes) (void)hipStreamSynchronize(ln.s);
 }
 
 ls_status check_solve_args(ls_server *sv, int64_t m, int64_t n, const double *A, int64_t lda,
@@ -484,8 +508,9 @@ ls_status ls_server_create(int device, int64_t budget_bytes, int32_t max_active,
     // map capacity: pass work-groups of max_active problems (at most 2048 each) plus their
     // reduction blocks (at most LS_MAX_N / 64 each)
     sv->wgmap_cap = (size_t)max_active * (2048 + LS_MAX_N / 64);
-    ok = ok && hipStreamCreateWithFlags(&sv->s_setup, hipStreamNonBlocking) == hipSuccess &&
-         hipStreamCreateWithFlags(&sv->s_serve, hipStreamNonBlocking) == hipSuccess &&
+    sv->lanes.resize(kSetupLanes);
+    for (auto &ln : sv->lanes) ok = ok && hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&sv->s_serve, hipStreamNonBlocking) == hipSuccess &&
          hipMalloc(&sv->d_slots, sizeof(ServeSlot) * (size_t)max_active) == hipSuccess &&
          hipMalloc(&sv->d_wgmap, sizeof(int32_t) * sv->wgmap_cap) == hipSuccess;
     sv->stage.resize(3);
@@ -522,7 +547,8 @@ void ls_server_destroy(ls_server *sv)
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(sv->device);
         if (sv->s_serve) (void)hipStreamSynchronize(sv->s_serve);
-        if (sv->s_setup) (void)hipStreamSynchronize(sv->s_setup);
+        for (auto &ln : sv->lanes)
+            if (ln.s) (void)hipStreamSynchronize(ln.s);
         for (auto &kv : sv->reqs) {
             if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
         }
@@ -534,10 +560,12 @@ void ls_server_destroy(ls_server *sv)
             if (st.ev) (void)hipEventDestroy(st.ev);
         }
         for (auto &e : sv->round_ev) if (e) (void)hipEventDestroy(e);
-        if (sv->ws) (void)hipFree(sv->ws);
+        for (auto &ln : sv->lanes)
+            if (ln.ws) (void)hipFree(ln.ws);
         if (sv->d_slots) (void)hipFree(sv->d_slots);
         if (sv->d_wgmap) (void)hipFree(sv->d_wgmap);
-        if (sv->s_setup) (void)hipStreamDestroy(sv->s_setup);
+        for (auto &ln : sv->lanes)
+            if (ln.s) (void)hipStreamDestroy(ln.s);
         if (sv->s_serve) (void)hipStreamDestroy(sv->s_serve);
         if (prev >= 0) (void)hipSetDevice(prev);
     }
