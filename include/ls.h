@@ -72,7 +72,9 @@ enum {
                                1: one launch per column (the fallback path)                     */
     LS_OPT_STOP = 9,        /* 1: ls_solve stops by the rule of Section 3.3, q being the maximum  */
     LS_OPT_GAMMA = 10,      /* gamma of that rule (dval, default 1)                              */
-    LS_OPT_RHO = 11         /* rho of that rule (dval, default 0.04)                             */
+    LS_OPT_RHO = 11,        /* rho of that rule (dval, default 0.04)                             */
+    LS_OPT_GATHER = 12      /* 0: the column-sliced sketch gather when the shape suits it (n >= 448,
+                               m >= 65536); 1: one wave per sketch row always.  Same bits.      */
 };
 ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval);
 ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval);
@@ -99,7 +101,9 @@ ls_status ls_sketch_csr(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t
 /* ---- Sketch (Algorithm 2, "B <- S A"; S b for the sketch-and-solve start, eq. sketched_ls) ------
  * B (d x n, ldb >= n) = S A and Sb (d) = S b for A (m x n, lda >= n), b (m).  Row k of B is the sum
  * of +-A[j, :] over the columns j of sketch row k in ascending j, then multiplied once by
- * fl(1/sqrt(zeta)).  Gathered by rows of A; no atomics.  b and Sb may both be NULL.
+ * fl(1/sqrt(zeta)).  Gathered by rows of A; each sum has a single writer that adds its terms in
+ * that order, so results are deterministic (and the same under LS_OPT_GATHER 0 and 1).  b and Sb
+ * may both be NULL.
  * Requires n >= 1, m >= 1, d >= 1, lda >= n, ldb >= n and the embedding limits above. */
 ls_status ls_sketch(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
                     const double *b, int64_t d, int32_t zeta, uint64_t seed, double *B, int64_t ldb,

@@ -264,7 +264,7 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
     IterBufs ib{};
     double *R = nullptr, *est_work = nullptr;
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
-        sketch_bufs(ar, m, d, zeta, sb);
+        sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather);
         qr_bufs(ar, d, n, qb);
         iter_bufs(ar, m, n, ib, false);
         R = ar.take<double>((size_t)n * (size_t)n);
@@ -273,7 +273,7 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
     // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
     LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw), "gather kernel");
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw, &sb.win), "gather kernel");
     // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
     HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
@@ -312,7 +312,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     float *R = nullptr, *est_work = nullptr;
     double *Sb = nullptr, *R64 = nullptr, *est64 = nullptr;
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
-        sketch_bufs(ar, m, d, zeta, sb);
+        sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather);
         qr_bufs(ar, d, n, qb64);
         qr_bufs(ar, d, n, qb);
         iter_bufs(ar, m, n, ib, false);
@@ -326,7 +326,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     // (a) FP64 sketch: B in the FP64 work matrix, S b contiguous; rounded copy for the FP32 QR.
     LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb64.W, qb64.ldw, Sb, 1), "gather kernel");
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb64.W, qb64.ldw, Sb, 1, &sb.win), "gather kernel");
     HIP_TRY(ctx, launch_round_sketch(s, d, n, qb64, Sb, qb), "round sketch");
     // (b) FP32 QR, R, the FP32 start, FP32 estimators; the fallback decision on the host.
     HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
@@ -482,6 +482,10 @@ ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval)
         if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "QR panel mode must be 0 or 1");
         ctx->qr_panel = (int32_t)ival;
         return LS_OK;
+    case LS_OPT_GATHER:
+        if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "gather mode must be 0 or 1");
+        ctx->gather = (int32_t)ival;
+        return LS_OK;
     case LS_OPT_STOP:
         if (ival != 0 && ival != 1) return ls_fail(ctx, LS_ERR_ARG, "stop must be 0 or 1");
         ctx->stop = (int32_t)ival;
@@ -512,6 +516,7 @@ ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval)
     case LS_OPT_PRECISION: iv = ctx->precision; break;
     case LS_OPT_PROFILE: iv = ctx->profile; break;
     case LS_OPT_QR_PANEL: iv = ctx->qr_panel; break;
+    case LS_OPT_GATHER: iv = ctx->gather; break;
     case LS_OPT_STOP: iv = ctx->stop; break;
     case LS_OPT_GAMMA: dv = ctx->gamma; break;
     case LS_OPT_RHO: dv = ctx->rho; break;
@@ -572,10 +577,10 @@ ls_status ls_sketch(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doubl
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     SketchBufs sb{};
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather); }));
     LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1), "gather kernel");
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1, &sb.win), "gather kernel");
     return LS_OK;
 }
 
@@ -661,10 +666,10 @@ ls_status ls_sketch_f32(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const d
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     SketchBufs sb{};
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb); }));
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather); }));
     LS_TRY(do_embedding(ctx, s, m, d, zeta, seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1), "gather kernel");
+    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, B, ldb, Sb, 1, &sb.win), "gather kernel");
     return LS_OK;
 }
 

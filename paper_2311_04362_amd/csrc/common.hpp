@@ -24,6 +24,7 @@ struct ls_ctx {
     int32_t precision = 0;          // 0 FP64, 1 mixed (FP32 sketch/QR/solves, FP64 pass/update)
     int32_t profile = 0;            // 1: bracket each fused-pass launch with events
     int32_t qr_panel = 0;           // 1: force the per-column panel path
+    int32_t gather = 0;             // 1: force the per-row sketch gather
     int32_t stop = 0;               // 1: Section 3.3 stopping rule in ls_solve
     double gamma = 1.0, rho = 0.04;
     // what the last ls_solve used (for ls_solve_info)
@@ -95,26 +96,48 @@ ls_status ls_ensure_ws(ls_ctx *ctx, size_t bytes);
 ls_status ls_hip_check(ls_ctx *ctx, hipError_t e, const char *what);
 
 // ---- sketch (sketch.hip) -------------------------------------------------------------------------
+// Entry lists of the column-sliced gather (k_gather_win).  Sketch rows are grouped by `rw`; the list
+// of a group holds its rows' CSR entries reordered window by window (windows of kWinLen rows of A),
+// rows in order inside a window, ascending j inside a row, so each row's terms keep their order.
+struct WinLists {
+    bool active = false;
+    int32_t rw = 0;        // sketch rows per group (one wave's accumulators)
+    int32_t nwl = 0;       // windows: ceil(m / kWinLen)
+    int32_t nstep = 0;     // barrier steps: ceil(nwl / kWinPerStep)
+    int32_t cus = 0;       // work-groups per XCD and launch (compute units per XCD)
+    uint32_t *lst = nullptr;   // m*zeta entries (j | sign<<31), group lists back to back
+    uint8_t *rloc = nullptr;   // m*zeta: row of each entry within its group
+    int32_t *ctab = nullptr;   // (nwl+1) x d: entries of row k in windows < w
+    int32_t *stab = nullptr;   // nwl x d: list offsets (k_win_scan)
+    int32_t *woff = nullptr;   // groups x (nstep+1): where each barrier step starts in a list
+};
 struct SketchBufs {
     uint32_t *ent;       // m*zeta packed (row | sign<<31), column-major by j
     int32_t *rowcount;   // d
     int32_t *rowptr;     // d+1
     int32_t *fill;       // d
     uint32_t *cols;      // m*zeta packed (j | sign<<31), by sketch row, ascending j
+    WinLists win;        // built by launch_csr when active
 };
-void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb);
+// n > 0 and win_mode == 0: also carve the lists of the column-sliced gather when the shape suits it.
+void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, int64_t n = 0,
+                 int32_t win_mode = 1);
 hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
                               const SketchBufs &sb);
 hipError_t launch_unpack_embedding(hipStream_t s, int64_t m, int32_t zeta, const uint32_t *ent,
                                    int32_t *rows, int8_t *signs);
 hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const SketchBufs &sb);
+// With active lists (win) the column-sliced gather runs, else one wave per sketch row; both add
+// the same terms in the same order and give the same bits.
 hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                          const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                         double *B, int64_t ldb, double *Sb, int64_t ldsb);
+                         double *B, int64_t ldb, double *Sb, int64_t ldsb,
+                         const WinLists *win = nullptr);
 // The same sums (FP64) stored rounded once to FP32, for the mixed-precision path.
 hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                          const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                         float *B, int64_t ldb, float *Sb, int64_t ldsb);
+                         float *B, int64_t ldb, float *Sb, int64_t ldsb,
+                         const WinLists *win = nullptr);
 
 // ---- QR (qr.hip) ---------------------------------------------------------------------------------
 // Buffers of the blocked Householder QR in element type E (double; float on the mixed path).

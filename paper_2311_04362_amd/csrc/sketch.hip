@@ -8,6 +8,16 @@
 //   k_gather        one wave per (sketch row, 64*CPL-column tile): B[k,:] = sum of +-A[j,:] over the
 //                   row's columns in ascending j, times fl(1/sqrt(zeta)).  Rows of A are read as
 //                   coalesced 512-byte segments (non-temporal); no atomics on floating-point data.
+//                   Every row of A is fetched from HBM once per nonzero of its column of S (zeta x).
+//   k_win_count, k_win_scan, k_win_scatter
+//                   reorder each group of sketch rows' CSR entries window by window (below).
+//   k_gather_win    the same sums with each row of A fetched from HBM about once: a work-group owns
+//                   a 64-column slice of 16*rw sketch rows, accumulated in LDS; the eight slices that
+//                   share rows of A run on the eight XCDs at the same time (one slice per XCD), and
+//                   a work-group barrier every kWinPerStep windows keeps the 16 waves of a CU within
+//                   a few thousand rows of A of each other, so the other nonzeros of a row of A
+//                   find it in that XCD's L2.  Each accumulator has one owner (its wave) and
+//                   receives its terms in ascending j, so the bits equal k_gather's.
 #include "common.hpp"
 
 namespace {
@@ -237,11 +247,185 @@ k_gather(int64_t n, int32_t ntiles, const double *__restrict__ A, int64_t lda,
     if (do_b) Sb[k * ldsb] = (OT)(sb * scale);
 }
 
+// ---- column-sliced gather -------------------------------------------------------------------------
+constexpr int kWinWaves = 16;          // waves per work-group (one group of rw sketch rows each)
+constexpr int kWinMaxRows = 20;        // rw at most: 16 x 20 x 64 doubles = 160 KiB of LDS
+constexpr int64_t kWinLen = 4096;      // rows of A per list window
+constexpr int kWinPerStep = 4;         // windows between two work-group barriers
+constexpr int kWinBatch = 16;          // rows of A in flight per wave
+
+// ctab[w*d + k] = entries of sketch row k in windows < w, for w = 0..nwl: entry p of the row
+// writes the windows (window of entry p-1, window of entry p], and p = L closes up to nwl, so every
+// (w, k) is written once.  One wave per row.
+__global__ void __launch_bounds__(256)
+k_win_count(int64_t d, int32_t nwl, const int32_t *__restrict__ rowptr,
+            const uint32_t *__restrict__ cols, int32_t *__restrict__ ctab)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= d) return;
+    const int32_t lo = rowptr[k], L = rowptr[k + 1] - lo;
+    for (int32_t p = lane; p <= L; p += 64) {
+        const int32_t w = (p < L) ? (int32_t)((cols[lo + p] & 0x7FFFFFFFu) / kWinLen) : nwl;
+        const int32_t wp = (p > 0) ? (int32_t)((cols[lo + p - 1] & 0x7FFFFFFFu) / kWinLen) : -1;
+        for (int32_t ww = wp + 1; ww <= w; ++ww) ctab[(int64_t)ww * d + k] = p;
+    }
+}
+
+// For group g (rows g*RW ..) and window w, the window-w entries of the group's row r start in the
+// group's list at  sum_{r' < r} ctab[w+1][r'] + sum_{r' > r} ctab[w][r']  plus the row's own entries
+// before window w; stab[w*d + k] holds the two sums.  woff[g][t] = where window t*kWinPerStep
+// starts in the list (absolute position in the entry arrays), woff[g][nstep] = the group's end.
+// One wave per (g, w); lanes are the group's rows.
+template <int RW>
+__global__ void __launch_bounds__(256)
+k_win_scan(int64_t d, int32_t nwl, int32_t nstep, const int32_t *__restrict__ rowptr,
+           const int32_t *__restrict__ ctab, int32_t *__restrict__ stab, int32_t *__restrict__ woff)
+{
+    const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t ngroups = (d + RW - 1) / RW;
+    if (pair >= ngroups * (int64_t)nwl) return;
+    const int64_t g = pair / nwl;
+    const int32_t w = (int32_t)(pair % nwl);
+    const int64_t k = g * RW + lane;
+    const bool row = lane < RW && k < d;
+    const int32_t c0 = row ? ctab[(int64_t)w * d + k] : 0;
+    const int32_t c1 = row ? ctab[(int64_t)(w + 1) * d + k] : 0;
+    int32_t pre = c1, suf = c0;      // inclusive prefix of c1, inclusive suffix of c0
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const int32_t up = __shfl_up(pre, off);
+        const int32_t dn = __shfl_down(suf, off);
+        if (lane >= off) pre += up;
+        if (lane + off < 64) suf += dn;
+    }
+    if (row) stab[(int64_t)w * d + k] = (pre - c1) + (suf - c0);
+    const int32_t *gp = rowptr + g * RW;
+    if (lane == 0 && w % kWinPerStep == 0) woff[g * (nstep + 1) + w / kWinPerStep] = gp[0] + suf;
+    if (lane == 0 && w == 0) {
+        const int64_t end = (g * RW + RW < d) ? g * RW + RW : d;
+        woff[g * (nstep + 1) + nstep] = rowptr[end];
+    }
+}
+
+// Places every CSR entry in its group's list; rloc records its row within the group.
+template <int RW>
+__global__ void __launch_bounds__(256)
+k_win_scatter(int64_t d, const int32_t *__restrict__ rowptr, const uint32_t *__restrict__ cols,
+              const int32_t *__restrict__ stab, uint32_t *__restrict__ lst, uint8_t *__restrict__ rloc)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= d) return;
+    const int64_t g = k / RW;
+    const int32_t gs = rowptr[g * RW];
+    const int32_t lo = rowptr[k], L = rowptr[k + 1] - lo;
+    for (int32_t p = lane; p < L; p += 64) {
+        const uint32_t v = cols[lo + p];
+        const int32_t w = (int32_t)((v & 0x7FFFFFFFu) / kWinLen);
+        const int32_t dst = gs + p + stab[(int64_t)w * d + k];
+        lst[dst] = v;
+        rloc[dst] = (uint8_t)(k - g * RW);
+    }
+}
+
+// Work-group (XCD x = blockIdx % 8, block blockIdx / 8) takes column slice slice0 + x and row block
+// rb0 + blockIdx / 8 (16 groups of RW sketch rows, one per wave).  Lane l of a wave owns column
+// 64*slice + l of its RW rows in LDS; column n is S b (lane reads b).  The wave walks its group's
+// list: 64 entries are read per vector load and broadcast by readlane, kWinBatch rows of A are in
+// flight, and each term goes to its row's accumulator by an LDS add in list order (one writer per
+// accumulator, so the order of each row's terms is the list's: ascending j).
+template <int RW, typename OT>
+__global__ void __launch_bounds__(kWinWaves * 64)
+k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0,
+             const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
+             const int32_t *__restrict__ woff, int32_t nstep, const uint32_t *__restrict__ lst,
+             const uint8_t *__restrict__ rloc, double scale, OT *__restrict__ B, int64_t ldb,
+             OT *__restrict__ Sb, int64_t ldsb)
+{
+    __shared__ double acc[kWinWaves * kWinMaxRows * 64];   // full size: one work-group per CU
+    const int slice = slice0 + (int)(blockIdx.x % 8);
+    if (slice >= nslice) return;
+    const int64_t rb = rb0 + blockIdx.x / 8;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t ngroups = (d + RW - 1) / RW;
+    const int64_t g = rb * kWinWaves + wave;
+    const bool live = g < ngroups;
+    const int64_t r0 = g * RW;
+    const int64_t r1 = live ? ((r0 + RW < d) ? r0 + RW : d) : r0;
+    const int64_t col = (int64_t)slice * 64 + lane;
+    const bool is_a = col < n;
+    const bool is_b = (col == n) && (b != nullptr);
+    // This lane's source column: A[:, col], b, or (no column) A[0, 0] read and never stored.
+    const double *src = is_a ? A + col : (is_b ? b : A);
+    const int64_t stride = is_a ? lda : (is_b ? 1 : 0);
+    double *my = acc + wave * RW * 64 + lane;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) my[r * 64] = 0.0;
+    const int32_t *wo = woff + (live ? g : 0) * (int64_t)(nstep + 1);
+    for (int32_t t = 0; t < nstep; ++t) {
+        const int32_t lo = live ? wo[t] : 0, hi = live ? wo[t + 1] : 0;
+        for (int32_t e0 = lo; e0 < hi; e0 += 64) {
+            const int cnt = (hi - e0 < 64) ? hi - e0 : 64;
+            const uint32_t vd = lane < cnt ? lst[e0 + lane] : 0u;
+            const int rd = lane < cnt ? (int)rloc[e0 + lane] : 0;
+            int u0 = 0;
+            for (; u0 + kWinBatch <= cnt; u0 += kWinBatch) {
+                uint32_t v[kWinBatch];
+                double a[kWinBatch];
+#pragma unroll
+                for (int u = 0; u < kWinBatch; ++u) {
+                    v[u] = __builtin_amdgcn_readlane(vd, u0 + u);
+                    a[u] = src[(int64_t)(v[u] & 0x7FFFFFFFu) * stride];
+                }
+#pragma unroll
+                for (int u = 0; u < kWinBatch; ++u) {
+                    const int r = __builtin_amdgcn_readlane(rd, u0 + u);
+                    atomicAdd(my + r * 64, (v[u] >> 31) ? -a[u] : a[u]);
+                }
+            }
+            for (; u0 < cnt; ++u0) {
+                const uint32_t v = __builtin_amdgcn_readlane(vd, u0);
+                const int r = __builtin_amdgcn_readlane(rd, u0);
+                const double a = src[(int64_t)(v & 0x7FFFFFFFu) * stride];
+                atomicAdd(my + r * 64, (v >> 31) ? -a : a);
+            }
+        }
+        __syncthreads();
+    }
+    if (is_a || is_b) {
+        OT *out = is_a ? B + col : Sb;
+        const int64_t ld = is_a ? ldb : ldsb;
+        for (int64_t r = r0; r < r1; ++r) out[r * ld] = (OT)(my[(r - r0) * 64] * scale);
+    }
+}
+
 inline unsigned blocks_for(int64_t count, int per) { return (unsigned)((count + per - 1) / per); }
+
+// Compute units per XCD of the current device (work-groups per XCD in one k_gather_win launch).
+int cus_per_xcd()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus >= 8 ? cus / 8 : 0;
+}
+
+// Rows per group for d sketch rows: the fewest launches of (8 XCDs x cus work-groups x 16 groups),
+// then the smallest multiple of 4 rows that covers d in that many launches.
+int32_t win_rows(int64_t d, int cus)
+{
+    const int64_t per = (int64_t)cus * kWinWaves;
+    const int64_t launches = (d + per * kWinMaxRows - 1) / (per * kWinMaxRows);
+    const int64_t rows = (d + launches * per - 1) / (launches * per);
+    return (int32_t)((rows + 3) / 4 * 4);
+}
 
 }  // namespace
 
-void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb)
+void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, int64_t n,
+                 int32_t win_mode)
 {
     const size_t nnz = (size_t)m * (size_t)zeta;
     sb.ent = ar.take<uint32_t>(nnz);
@@ -249,6 +433,23 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb)
     sb.rowptr = ar.take<int32_t>((size_t)d + 1);
     sb.fill = ar.take<int32_t>((size_t)d);
     sb.cols = ar.take<uint32_t>(nnz);
+    sb.win = WinLists{};
+    // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
+    // slices keep the eight XCDs busy and A is large.
+    const int cus = (win_mode == 0 && n >= 448 && m >= 65536 && d >= 64) ? cus_per_xcd() : 0;
+    if (cus == 0) return;
+    WinLists &w = sb.win;
+    w.active = true;
+    w.cus = cus;
+    w.rw = win_rows(d, cus);
+    w.nwl = (int32_t)((m + kWinLen - 1) / kWinLen);
+    w.nstep = (w.nwl + kWinPerStep - 1) / kWinPerStep;
+    const int64_t ngroups = (d + w.rw - 1) / w.rw;
+    w.lst = ar.take<uint32_t>(nnz);
+    w.rloc = ar.take<uint8_t>(nnz);
+    w.ctab = ar.take<int32_t>((size_t)(w.nwl + 1) * (size_t)d);
+    w.stab = ar.take<int32_t>((size_t)w.nwl * (size_t)d);
+    w.woff = ar.take<int32_t>((size_t)ngroups * (size_t)(w.nstep + 1));
 }
 
 hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
@@ -276,16 +477,65 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
     hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, zeta, sb.ent,
                        sb.rowptr, sb.fill, sb.cols);
     hipLaunchKernelGGL(k_csr_sort, dim3((unsigned)d), dim3(256), 0, s, d, sb.rowptr, sb.cols);
+    if (!sb.win.active) return hipGetLastError();
+    const WinLists &w = sb.win;
+    const int64_t ngroups = (d + w.rw - 1) / w.rw;
+    const unsigned row_blocks = blocks_for(d, 4), pair_blocks = blocks_for(ngroups * w.nwl, 4);
+    hipLaunchKernelGGL(k_win_count, dim3(row_blocks), dim3(256), 0, s, d, w.nwl, sb.rowptr, sb.cols, w.ctab);
+    switch (w.rw) {
+#define LS_WIN_CASE(R)                                                                                   \
+    case R:                                                                                              \
+        hipLaunchKernelGGL(k_win_scan<R>, dim3(pair_blocks), dim3(256), 0, s, d, w.nwl, w.nstep,        \
+                           sb.rowptr, w.ctab, w.stab, w.woff);                                           \
+        hipLaunchKernelGGL(k_win_scatter<R>, dim3(row_blocks), dim3(256), 0, s, d, sb.rowptr, sb.cols,   \
+                           w.stab, w.lst, w.rloc);                                                       \
+        break;
+    LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
+#undef LS_WIN_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 namespace {
 
+// One launch per (group of eight slices, share of the row blocks): every launch fills each XCD's
+// compute units with one work-group each, all starting together.
+template <typename OT>
+hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
+                      const double *b, double scale, OT *B, int64_t ldb, OT *Sb, int64_t ldsb,
+                      const WinLists &w)
+{
+    const int32_t nslice = (int32_t)((n + (b ? 1 : 0) + 63) / 64);
+    const int64_t ngroups = (d + w.rw - 1) / w.rw;
+    const int64_t nrb = (ngroups + kWinWaves - 1) / kWinWaves;
+    const int64_t launches = (nrb + w.cus - 1) / w.cus;
+    for (int32_t s0 = 0; s0 < nslice; s0 += 8) {
+        for (int64_t l = 0; l < launches; ++l) {
+            const int64_t rb0 = nrb * l / launches, rb1 = nrb * (l + 1) / launches;
+            const dim3 grid((unsigned)(8 * (rb1 - rb0)));
+            switch (w.rw) {
+#define LS_WIN_CASE(R)                                                                                   \
+            case R:                                                                                      \
+                hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, \
+                                   s0, rb0, A, lda, b, w.woff, w.nstep, w.lst, w.rloc, scale, B, ldb,     \
+                                   Sb, ldsb);                                                            \
+                break;
+            LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
+#undef LS_WIN_CASE
+            default: return hipErrorInvalidValue;
+            }
+        }
+    }
+    return hipGetLastError();
+}
+
 template <typename OT>
 hipError_t gather_impl(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                        const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                       OT *B, int64_t ldb, OT *Sb, int64_t ldsb)
+                       OT *B, int64_t ldb, OT *Sb, int64_t ldsb, const WinLists *win)
 {
+    if (win && win->active) return gather_win(s, d, n, A, lda, b, scale, B, ldb, Sb, ldsb, *win);
     // Columns per lane: the smallest of 1, 2, 4, 8 covering n in one tile, else tiles of 512.
     int cpl = 8;
     if (n <= 64) cpl = 1;
@@ -306,14 +556,14 @@ hipError_t gather_impl(hipStream_t s, int64_t d, int64_t n, const double *A, int
 
 hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                          const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                         double *B, int64_t ldb, double *Sb, int64_t ldsb)
+                         double *B, int64_t ldb, double *Sb, int64_t ldsb, const WinLists *win)
 {
-    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb);
+    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb, win);
 }
 
 hipError_t launch_gather(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                          const double *b, const int32_t *rowptr, const uint32_t *cols, double scale,
-                         float *B, int64_t ldb, float *Sb, int64_t ldsb)
+                         float *B, int64_t ldb, float *Sb, int64_t ldsb, const WinLists *win)
 {
-    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb);
+    return gather_impl(s, d, n, A, lda, b, rowptr, cols, scale, B, ldb, Sb, ldsb, win);
 }

@@ -19,7 +19,7 @@ LS_OK, LS_ERR_ARG, LS_ERR_ALLOC, LS_ERR_DEVICE, LS_ERR_RANK, LS_ERR_NONFINITE, \
 STATUS_NAMES = ["LS_OK", "LS_ERR_ARG", "LS_ERR_ALLOC", "LS_ERR_DEVICE", "LS_ERR_RANK",
                 "LS_ERR_NONFINITE", "LS_ERR_DIVERGED", "LS_ERR_UNSUPPORTED", "LS_ERR_TIMEOUT"]
 OPT_ZETA, OPT_SEED, OPT_UPDATE, OPT_ALPHA, OPT_BETA, OPT_PRECISION, OPT_PROFILE, OPT_QR_PANEL, \
-    OPT_STOP, OPT_GAMMA, OPT_RHO = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+    OPT_STOP, OPT_GAMMA, OPT_RHO, OPT_GATHER = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 NORMEST_SEED_OFFSET = 0x632BE59BD9B4E019
 PRECISION_FP64, PRECISION_MIXED, PRECISION_FELL_BACK_COND, PRECISION_FELL_BACK_GROWTH = 0, 1, 2, 3
 

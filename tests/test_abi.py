@@ -86,6 +86,13 @@ def test_options_roundtrip(L, hctx):
     assert iv.value == 12345
     assert L.ls_set_option(hctx, ls.OPT_UPDATE, 3, 0.0) == ls.LS_ERR_ARG
     assert L.ls_set_option(hctx, ls.OPT_ALPHA, 0, float("nan")) == ls.LS_ERR_ARG
+    assert L.ls_get_option(hctx, ls.OPT_GATHER, ctypes.byref(iv), ctypes.byref(dv)) == ls.LS_OK
+    assert iv.value == 0
+    assert L.ls_set_option(hctx, ls.OPT_GATHER, 1, 0.0) == ls.LS_OK
+    L.ls_get_option(hctx, ls.OPT_GATHER, ctypes.byref(iv), ctypes.byref(dv))
+    assert iv.value == 1
+    assert L.ls_set_option(hctx, ls.OPT_GATHER, 2, 0.0) == ls.LS_ERR_ARG
+    assert L.ls_set_option(hctx, ls.OPT_GATHER, 0, 0.0) == ls.LS_OK
     assert L.ls_set_option(hctx, 999, 0, 0.0) == ls.LS_ERR_ARG
     assert b"unknown" in L.ls_last_error(hctx)
 

@@ -67,6 +67,14 @@ def test_fullsize_sketch_rows_and_qr(big):
         sg = es[jj, ee]
         assert np.array_equal(Bh[k], oracle.sketch_row(rows_k, sg, 8))
         assert Sbh[k] == oracle.sketch_row(bk, sg, 8)[0]
+    # the whole sketch equals the per-row gather's (LS_OPT_GATHER = 1) bit for bit
+    ctx.set_option(ls.OPT_GATHER, 1)
+    try:
+        B1, Sb1 = ctx.sketch(A, p.b, d, 8, s)
+    finally:
+        ctx.set_option(ls.OPT_GATHER, 0)
+    assert torch.equal(B1, B) and torch.equal(Sb1, Sb)
+    del B1, Sb1
     # QR of this sketch against the oracle's Householder QR of the same B, Sb
     R, x0 = ctx.qr_sketch(B, Sb)
     ctx.sync()

@@ -1,0 +1,118 @@
+"""GPU parity of the column-sliced sketch gather (k_gather_win, LS_OPT_GATHER = 0) that ls_sketch,
+ls_sketch_f32 and ls_solve use when n >= 448 and m >= 65536.
+
+Each sketch row is the sum of +-A[j, :] over its columns in ascending j, times fl(1/sqrt(zeta))
+(eq. sparse_sign; Algorithm 2, "B <- S A").  The column-sliced gather adds the same terms in the
+same order as the oracle's loop over j, so every case is bit-exact against the oracle, and against
+the per-row gather (LS_OPT_GATHER = 1).  The shapes cover: m not a multiple of the 4096-row list
+window; d not a multiple of a work-group's rows; rows per group of 4, 12 and 20; more than one launch
+per slice group; S b alone in a last slice (n = 513), or starting a slice (n = 640); no right-hand
+side; padded lda and ldb; FP32 output; and subnormal inputs, whose sums stay subnormal."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2311_04362_amd import ls  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ls.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def sketch_mode(ctx, mode, *args, **kw):
+    ctx.set_option(ls.OPT_GATHER, mode)
+    try:
+        return ctx.sketch(*args, **kw)
+    finally:
+        ctx.set_option(ls.OPT_GATHER, 0)
+
+
+# (m, n, d): rows per group 4 (d = 1000), 20 (d = 10007), 12 with two launches (d = 12000).
+@pytest.mark.parametrize("m,n,d", [(70001, 448, 1000), (70001, 500, 10007), (65536, 513, 3000),
+                                   (70001, 640, 2001), (66000, 1000, 12000)])
+def test_window_gather_bit_exact(ctx, m, n, d):
+    rng = np.random.default_rng(m + 3 * n + d)
+    lda = n + 5
+    A = np.zeros((m, lda))
+    A[:, :n] = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    B, Sb = ctx.sketch(dev(A)[:, :n], dev(b), d, 8, 31)
+    eB, eSb = oracle.sketch(A[:, :n], b, n, d, 8, 31)
+    assert np.array_equal(host(B), eB)
+    assert np.array_equal(host(Sb), eSb)
+    B1, Sb1 = sketch_mode(ctx, 1, dev(A)[:, :n], dev(b), d, 8, 31)
+    assert np.array_equal(host(B1), eB)
+    assert np.array_equal(host(Sb1), eSb)
+
+
+def test_window_gather_no_rhs_padded_ldb(ctx):
+    m, n, d = 70001, 500, 4000
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    eB, _ = oracle.sketch(A, b, n, d, 8, 12)
+    B, Sb = ctx.sketch(dev(A), None, d, 8, 12)
+    assert Sb is None
+    assert np.array_equal(host(B), eB)
+    Bp = torch.full((d, n + 9), 7.0, dtype=torch.float64, device="cuda")
+    ctx.sketch(dev(A), dev(b), d, 8, 12, B=Bp[:, :n])
+    assert np.array_equal(host(Bp)[:, :n], eB)
+    assert np.all(host(Bp)[:, n:] == 7.0)          # nothing written past column n-1
+
+
+def test_window_gather_f32(ctx):
+    m, n, d = 70001, 500, 10000
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    B, Sb = ctx.sketch_f32(dev(A), dev(b), d, 8, 17)
+    eB, eSb = oracle.sketch(A, b, n, d, 8, 17)
+    assert np.array_equal(host(B), eB.astype(np.float32))
+    assert np.array_equal(host(Sb), eSb.astype(np.float32))
+
+
+def test_window_gather_subnormal(ctx):
+    # Entries near 2^-1060: every partial sum is subnormal, so any flush to zero or other rounding
+    # of the LDS additions would change bits.
+    m, n, d = 70001, 500, 2000
+    rng = np.random.default_rng(9)
+    A = rng.integers(-2 ** 20, 2 ** 20, size=(m, n)).astype(np.float64) * 2.0 ** -1074
+    A[:, 7] = rng.standard_normal(m) * 1e-300          # one column of normal numbers
+    b = rng.standard_normal(m) * 2.0 ** -1040
+    B, Sb = ctx.sketch(dev(A), dev(b), d, 8, 4)
+    eB, eSb = oracle.sketch(A, b, n, d, 8, 4)
+    assert np.any((eB != 0) & (np.abs(eB) < 2.2250738585072014e-308))
+    assert np.array_equal(host(B), eB)
+    assert np.array_equal(host(Sb), eSb)
+
+
+def test_solve_same_bits_both_gathers(ctx):
+    m, n, d = 70001, 500, 5000
+    rng = np.random.default_rng(10)
+    A = dev(rng.standard_normal((m, n)))
+    b = dev(rng.standard_normal(m))
+    x0 = host(ctx.solve(A, b, d, 5))
+    ctx.set_option(ls.OPT_GATHER, 1)
+    try:
+        x1 = host(ctx.solve(A, b, d, 5))
+    finally:
+        ctx.set_option(ls.OPT_GATHER, 0)
+    ctx.sync()
+    assert np.array_equal(x0, x1)
