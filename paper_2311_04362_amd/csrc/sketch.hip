@@ -5,6 +5,8 @@
 //   k_scan_rows     exclusive scan of the row histogram -> CSR row pointers.
 //   k_csr_scatter   places each nonzero in its sketch row (slot order within a row is arbitrary).
 //   k_csr_sort      sorts every sketch row by column index j, making the CSR unique: ascending j.
+//   k_chunk_*       the same CSR for d <= kLdsRows from per-chunk LDS histograms, without global
+//                   atomics and without the row sort (below); k_sparse_sign then skips its histogram.
 //   k_gather        one wave per (sketch row, 64*CPL-column tile): B[k,:] = sum of +-A[j,:] over the
 //                   row's columns in ascending j, times fl(1/sqrt(zeta)).  Rows of A are read as
 //                   coalesced 512-byte segments (non-temporal); no atomics on floating-point data.
@@ -35,7 +37,7 @@ __device__ __forceinline__ uint64_t splitmix_out(uint64_t seed, uint64_t k)
 
 __global__ void __launch_bounds__(256)
 k_sparse_sign(int64_t m, uint64_t d, int32_t zeta, uint64_t seed, uint32_t *__restrict__ ent,
-              int32_t *__restrict__ rowcount)
+              int32_t *__restrict__ rowcount)   // rowcount == nullptr: no histogram
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
@@ -53,7 +55,7 @@ k_sparse_sign(int64_t m, uint64_t d, int32_t zeta, uint64_t seed, uint32_t *__re
         for (int e = 0; e < LS_MAX_ZETA; ++e)
             if (e == got) taken[e] = row;
         out[got] = row | ((uint32_t)(z & 1ULL) << 31);
-        atomicAdd(&rowcount[row], 1);
+        if (rowcount) atomicAdd(&rowcount[row], 1);
         ++got;
     }
     for (uint32_t row = 0; got < zeta; ++row) {   // exhausted draws: smallest free rows, sign +1
@@ -65,7 +67,7 @@ k_sparse_sign(int64_t m, uint64_t d, int32_t zeta, uint64_t seed, uint32_t *__re
         for (int e = 0; e < LS_MAX_ZETA; ++e)
             if (e == got) taken[e] = row;
         out[got] = row;
-        atomicAdd(&rowcount[row], 1);
+        if (rowcount) atomicAdd(&rowcount[row], 1);
         ++got;
     }
 }
@@ -176,6 +178,94 @@ k_csr_sort(int64_t d, const int32_t *__restrict__ rowptr, uint32_t *__restrict__
     }
     if (in_lds) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) cols[lo + i] = buf[i];
+    }
+}
+
+// ---- CSR by chunk histograms (d <= kLdsRows) -------------------------------------------------------
+// The columns of S are cut into chunks of kChunkCols.  A work-group counts its chunk's nonzeros per
+// sketch row in LDS; the counts are summed over chunks (row lengths, then rowptr by k_scan_rows) and
+// turned in place into each (chunk, row) segment's start; a work-group then places its chunk's
+// nonzeros in their segments (LDS counters) and sorts each segment, a handful of entries, by j.
+// Segments of one row follow chunk order, so every row ends in ascending j: the CSR of k_csr_sort.
+constexpr int kChunkCols = 8192;
+constexpr int64_t kLdsRows = 32768;
+
+__global__ void __launch_bounds__(1024)
+k_chunk_hist(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ ent,
+             int32_t *__restrict__ cnt)
+{
+    __shared__ int32_t h[kLdsRows];
+    const int64_t c = blockIdx.x;
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const int64_t j1 = ((c + 1) * kChunkCols < m) ? (c + 1) * kChunkCols : m;
+    for (int64_t i = c * kChunkCols * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x)
+        atomicAdd(&h[ent[i] & 0x7FFFFFFFu], 1);
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) cnt[c * d + k] = h[k];
+}
+
+// rowcount[k] = sum over chunks of cnt[c][k], in chunk order.  One thread per row.
+__global__ void __launch_bounds__(256)
+k_chunk_total(int64_t d, int32_t nchunk, const int32_t *__restrict__ cnt, int32_t *__restrict__ rowcount)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d) return;
+    rowcount[k] = strided_sum<8>(cnt + k, nchunk, d);
+}
+
+// cnt[c][k] <- rowptr[k] + sum over chunks c' < c of cnt[c'][k] (start of the chunk's segment).
+__global__ void __launch_bounds__(256)
+k_chunk_base(int64_t d, int32_t nchunk, const int32_t *__restrict__ rowptr, int32_t *__restrict__ cnt)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d) return;
+    int32_t run = rowptr[k];
+    int32_t c = 0;
+    for (; c + 8 <= nchunk; c += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(c + u) * d + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            cnt[(int64_t)(c + u) * d + k] = run;
+            run += v[u];
+        }
+    }
+    for (; c < nchunk; ++c) {
+        const int32_t v = cnt[(int64_t)c * d + k];
+        cnt[(int64_t)c * d + k] = run;
+        run += v;
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_chunk_place(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ ent,
+              const int32_t *__restrict__ base, uint32_t *__restrict__ cols)
+{
+    __shared__ int32_t pos[kLdsRows];
+    const int64_t c = blockIdx.x;
+    const int32_t *b = base + c * d;
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) pos[k] = b[k];
+    __syncthreads();
+    const int64_t j1 = ((c + 1) * kChunkCols < m) ? (c + 1) * kChunkCols : m;
+    for (int64_t i = c * kChunkCols * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x) {
+        const uint32_t v = ent[i];
+        const int32_t p = atomicAdd(&pos[v & 0x7FFFFFFFu], 1);
+        cols[p] = (uint32_t)(i / zeta) | (v & 0x80000000u);
+    }
+    __syncthreads();   // this work-group's entries are in place (visible to the work-group)
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) {
+        const int32_t lo = b[k], hi = pos[k];
+        for (int32_t i = lo + 1; i < hi; ++i) {      // insertion sort by j of a few entries
+            const uint32_t x = cols[i];
+            int32_t q = i - 1;
+            while (q >= lo && (cols[q] & 0x7FFFFFFFu) > (x & 0x7FFFFFFFu)) {
+                cols[q + 1] = cols[q];
+                --q;
+            }
+            cols[q + 1] = x;
+        }
     }
 }
 
@@ -433,6 +523,8 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
     sb.rowptr = ar.take<int32_t>((size_t)d + 1);
     sb.fill = ar.take<int32_t>((size_t)d);
     sb.cols = ar.take<uint32_t>(nnz);
+    const size_t chunk_cells = (size_t)((m + kChunkCols - 1) / kChunkCols) * (size_t)d;
+    sb.chunk_cnt = (d <= kLdsRows && chunk_cells <= ((size_t)1 << 26)) ? ar.take<int32_t>(chunk_cells) : nullptr;
     sb.win = WinLists{};
     // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
     // slices keep the eight XCDs busy and A is large.
@@ -455,10 +547,14 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
 hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
                               const SketchBufs &sb)
 {
-    hipError_t e = hipMemsetAsync(sb.rowcount, 0, sizeof(int32_t) * (size_t)d, s);
-    if (e != hipSuccess) return e;
+    int32_t *count = nullptr;          // the chunk path counts rows itself, without global atomics
+    if (!sb.chunk_cnt) {
+        hipError_t e = hipMemsetAsync(sb.rowcount, 0, sizeof(int32_t) * (size_t)d, s);
+        if (e != hipSuccess) return e;
+        count = sb.rowcount;
+    }
     hipLaunchKernelGGL(k_sparse_sign, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, (uint64_t)d,
-                       zeta, seed, sb.ent, sb.rowcount);
+                       zeta, seed, sb.ent, count);
     return hipGetLastError();
 }
 
@@ -473,10 +569,19 @@ hipError_t launch_unpack_embedding(hipStream_t s, int64_t m, int32_t zeta, const
 hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const SketchBufs &sb)
 {
     const int64_t nnz = m * zeta;
-    hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, d, sb.rowcount, sb.rowptr, sb.fill);
-    hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, zeta, sb.ent,
-                       sb.rowptr, sb.fill, sb.cols);
-    hipLaunchKernelGGL(k_csr_sort, dim3((unsigned)d), dim3(256), 0, s, d, sb.rowptr, sb.cols);
+    if (sb.chunk_cnt) {
+        const int32_t nchunk = (int32_t)((m + kChunkCols - 1) / kChunkCols);
+        hipLaunchKernelGGL(k_chunk_hist, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, sb.ent, sb.chunk_cnt);
+        hipLaunchKernelGGL(k_chunk_total, dim3(blocks_for(d, 256)), dim3(256), 0, s, d, nchunk, sb.chunk_cnt, sb.rowcount);
+        hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, d, sb.rowcount, sb.rowptr, sb.fill);
+        hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(d, 256)), dim3(256), 0, s, d, nchunk, sb.rowptr, sb.chunk_cnt);
+        hipLaunchKernelGGL(k_chunk_place, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, sb.ent, sb.chunk_cnt, sb.cols);
+    } else {
+        hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, d, sb.rowcount, sb.rowptr, sb.fill);
+        hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, zeta, sb.ent,
+                           sb.rowptr, sb.fill, sb.cols);
+        hipLaunchKernelGGL(k_csr_sort, dim3((unsigned)d), dim3(256), 0, s, d, sb.rowptr, sb.cols);
+    }
     if (!sb.win.active) return hipGetLastError();
     const WinLists &w = sb.win;
     const int64_t ngroups = (d + w.rw - 1) / w.rw;
