@@ -151,7 +151,6 @@ struct QrBufsT {
     E *tau;              // n
     E *Yp;               // chunk partials of V^T [V | C]
     E *Z;                // NB x ldw
-    E *T;                // NB x NB
     E *qtb;              // n
     E *RT;               // n x n  (R^T, row-major)
     unsigned *bar;       // grid-barrier counter of the cooperative panel kernel

@@ -10,10 +10,11 @@
 //
 // After the panel, the compact-WY form Q_p = I - V T V^T (T upper triangular) is built and the
 // trailing columns -- including the S b column, so Q is never formed -- are updated as
-// C <- C - V (T^T (V^T C)).  Both products run on the matrix cores (v_mfma_f64_16x16x4f64, or
-// v_mfma_f32_16x16x4f32 for the single-precision factorization of the mixed-precision path);
-// V^T C is split over row chunks whose partial products are summed in a fixed order, so the
-// factorization is deterministic.  Every kernel is instantiated for FP64 and FP32.
+// C <- C - V (T^T (V^T C)) by three launches: V^T [V | C] over row chunks (k_vx_partial), the chunk
+// sums with T and Z = T^T V^T C (k_tz), and C -= V Z (k_update_c).  Both products run on the matrix
+// cores (v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 for the single-precision factorization of
+// the mixed-precision path); every reduction has a fixed order, so the factorization is
+// deterministic.  Every kernel is instantiated for FP64 and FP32.
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -257,6 +258,10 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
     __shared__ E s_scal[2];
     __shared__ E s_piv[kNB];
     __shared__ int s_haspiv;
+    // The panel's Householder vectors for this work-group's rows, column-major (conflict-free):
+    // written to V once after the last column, so the barriers' release fences do not also push
+    // V stores out of L2 at every column.
+    __shared__ E s_v[kNB][RPT * kRB];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     E *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
     const int tidx = transpose_sum_index(lane);
@@ -363,7 +368,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             if (!ok[r]) continue;
             const bool below = row[r] >= k;
             const E vi = (row[r] == k) ? s_scal[1] : w[r][jc];
-            V[(row[r] - p0) * kNB + jc] = below ? vi : E(0);
+            s_v[jc][r * kRB + tid] = below ? vi : E(0);
             if (!below) continue;
 #pragma unroll
             for (int l = jc + 1; l < kNB; ++l)
@@ -378,6 +383,9 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
 #pragma unroll
         for (int l = 0; l < kNB; ++l)
             if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
+        E *vrow = V + (row[r] - p0) * kNB;
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) vrow[l] = (l < nbp) ? s_v[l][r * kRB + tid] : E(0);
     }
 }
 
@@ -387,115 +395,120 @@ __global__ void k_zero_u32(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
-// out[ch][a][c] = sum over rows r of chunk ch of V[r][a] X[r][c]  (a < kNB, c < ncx).
-// Work-group tile: kNB x 64 columns; wave w computes columns 16w..16w+15 for both 16-row halves.
-// Operands and accumulator rows as in Mfma<E>.
+// P[ch][a][c] = sum over the rows r of chunk ch of V[r][a] X[r][c], for X = [V | C] (column c < kNB
+// of X is column c of V, column c >= kNB is column c - kNB of C), a < kNB, c < nx = kNB + nc.
+// Work-group: 64 columns of X.  Its four waves take interleaved groups of 4 rows of the chunk
+// (split-K), each wave 32 x 64 in eight MFMA accumulators; the waves' results are added in wave
+// order through LDS, so the partial is deterministic.  Operand and accumulator rows as in Mfma<E>.
 template <typename E>
 __global__ void __launch_bounds__(256)
-k_vtx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V,
-              const E *__restrict__ X, int64_t ldx, int64_t ncx, int64_t ldo,
-              E *__restrict__ out)
+k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__restrict__ C,
+             int64_t ldc, int64_t nx, int64_t ldo, E *__restrict__ P)
 {
+    __shared__ E s_acc[4][kNB][64 + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t ch = blockIdx.x;
     const int64_t r_lo = ch * chunk;
     const int64_t r_hi = (r_lo + chunk < rows) ? r_lo + chunk : rows;
-    const int64_t col = (int64_t)blockIdx.y * 64 + 16 * wave + (lane & 15);
-    const bool col_ok = col < ncx;
     const int kk = lane >> 4, ii = lane & 15;
-    typename Mfma<E>::v4 acc0 = {E(0), E(0), E(0), E(0)}, acc1 = {E(0), E(0), E(0), E(0)};
-    for (int64_t r = r_lo; r < r_hi; r += 4) {
+    // Column 16 s + ii of this block, s < 4: its source array, leading dimension and validity.
+    const E *src[4];
+    int64_t lds[4];
+    bool cok[4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+        const int64_t col = (int64_t)blockIdx.y * 64 + 16 * sb + ii;
+        cok[sb] = col < nx;
+        src[sb] = (col < kNB) ? V + col : C + (col - kNB);
+        lds[sb] = (col < kNB) ? (int64_t)kNB : ldc;
+    }
+    typename Mfma<E>::v4 acc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) acc[h][sb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
+    for (int64_t r = r_lo + 4 * wave; r < r_hi; r += 16) {
         const int64_t rr = r + kk;
         const bool ok = rr < r_hi;
         const E a0 = ok ? V[rr * kNB + ii] : E(0);
         const E a1 = ok ? V[rr * kNB + 16 + ii] : E(0);
-        const E bb = (ok && col_ok) ? X[rr * ldx + col] : E(0);
-        acc0 = Mfma<E>::mma(a0, bb, acc0);
-        acc1 = Mfma<E>::mma(a1, bb, acc1);
+        E bv[4];
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) bv[sb] = (ok && cok[sb]) ? src[sb][rr * lds[sb]] : E(0);
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+            acc[0][sb] = Mfma<E>::mma(a0, bv[sb], acc[0][sb]);
+            acc[1][sb] = Mfma<E>::mma(a1, bv[sb], acc[1][sb]);
+        }
     }
-    if (col_ok) {
-        E *o = out + ch * (int64_t)kNB * ldo + col;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int a = Mfma<E>::row(q, lane);
-            o[(int64_t)a * ldo] = acc0[q];
-            o[(int64_t)(16 + a) * ldo] = acc1[q];
+            s_acc[wave][a][16 * sb + ii] = acc[0][sb][q];
+            s_acc[wave][16 + a][16 * sb + ii] = acc[1][sb][q];
         }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNB * 64; e += blockDim.x) {
+        const int a = e / 64, c = e % 64;
+        const int64_t col = (int64_t)blockIdx.y * 64 + c;
+        if (col >= nx) continue;
+        const E t = ((s_acc[0][a][c] + s_acc[1][a][c]) + s_acc[2][a][c]) + s_acc[3][a][c];
+        P[(ch * kNB + a) * ldo + col] = t;
     }
 }
 
-// T of the compact-WY form: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+// For one 64-column block of the trailing columns: G = V^T V and Y = V^T C are the chunk sums of P
+// (added in chunk order); T is the compact-WY factor, T[j][j] = tau_j and T[0:j, j] =
+// -tau_j T[0:j, 0:j] G[0:j, j], formed by every work-group in its first wave; then
+// Z[:, c] = T^T Y[:, c].
 template <typename E>
-__global__ void __launch_bounds__(256)
-k_form_t(int nch, int64_t ldo, const E *__restrict__ Gp, const E *__restrict__ tau,
-         int64_t p0, int nbp, E *__restrict__ T)
+__global__ void __launch_bounds__(1024)
+k_tz(int nch, int64_t ldo, const E *__restrict__ P, const E *__restrict__ tau, int64_t p0, int nbp,
+     int64_t nc, E *__restrict__ Z, int64_t ldz)
 {
     __shared__ E G[kNB][kNB + 1];
     __shared__ E Ts[kNB][kNB + 1];
+    __shared__ E Y[kNB][64 + 1];
+    __shared__ E s_tau[kNB];
     const int tid = threadIdx.x;
-    for (int e = tid; e < kNB * kNB; e += blockDim.x) {
-        const int a = e / kNB, c = e % kNB;
-        G[a][c] = strided_sum<8>(Gp + (int64_t)a * ldo + c, nch, (int64_t)kNB * ldo);
+    const int64_t pstride = (int64_t)kNB * ldo;
+    if (tid < kNB) s_tau[tid] = (tid < nbp) ? tau[p0 + tid] : E(0);
+    {
+        const int a = tid / kNB, c = tid % kNB;
+        G[a][c] = strided_sum<8>(P + (int64_t)a * ldo + c, nch, pstride);
         Ts[a][c] = E(0);
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = tid + h * 1024;
+        const int a = e / 64, cl = e % 64;
+        const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+        Y[a][cl] = (c < nc) ? strided_sum<8>(P + (int64_t)a * ldo + kNB + c, nch, pstride) : E(0);
+    }
     __syncthreads();
-    for (int j = 0; j < nbp; ++j) {
-        const E tj = tau[p0 + j];
-        if (tid < j) {
+    // Row i of T needs only its own earlier entries: T[i][j] = -tau_j sum_{q=i}^{j-1} T[i][q] G[q][j],
+    // summed in ascending q.  Lane i of the first wave forms row i (it reads back only its own row).
+    if (tid < nbp) {
+        const int i = tid;
+        Ts[i][i] = s_tau[i];
+        for (int j = i + 1; j < nbp; ++j) {
             E acc = E(0);
-            for (int q = tid; q < j; ++q) acc += Ts[tid][q] * G[q][j];
-            Ts[tid][j] = -tj * acc;
-        }
-        if (tid == 0) Ts[j][j] = tj;
-        __syncthreads();
-    }
-    for (int e = tid; e < kNB * kNB; e += blockDim.x) T[e] = Ts[e / kNB][e % kNB];
-}
-
-// Z[:, c] = T^T (sum over chunks of Yp[:, :, c]) for every trailing column c.  Four threads per
-// column each sum a contiguous quarter of the chunks; the quarters are added in order.
-constexpr int kApplyCols = 32;
-constexpr int kApplySlices = 4;
-
-template <typename E>
-__global__ void __launch_bounds__(kApplyCols * kApplySlices)
-k_apply_t(int nch, int64_t ldo, const E *__restrict__ Yp, const E *__restrict__ T,
-          int64_t nc, E *__restrict__ Z, int64_t ldz)
-{
-    __shared__ E Ts[kNB * kNB];
-    __shared__ E ys[kApplySlices][kNB][kApplyCols + 1];
-    for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) Ts[e] = T[e];
-    const int cl = threadIdx.x % kApplyCols, sl = threadIdx.x / kApplyCols;
-    const int64_t c = (int64_t)blockIdx.x * kApplyCols + cl;
-    const int per = (nch + kApplySlices - 1) / kApplySlices;
-    const int g0 = sl * per;
-    const int cnt = (g0 + per < nch) ? per : (nch > g0 ? nch - g0 : 0);
-    E y[kNB];
-#pragma unroll
-    for (int a = 0; a < kNB; ++a) y[a] = E(0);
-    if (c < nc) {
-        for (int g = g0; g < g0 + cnt; ++g) {
-            const E *p = Yp + (int64_t)g * kNB * ldo + c;
-#pragma unroll
-            for (int a = 0; a < kNB; ++a) y[a] += p[(int64_t)a * ldo];
+#pragma unroll 8
+            for (int q = i; q < j; ++q) acc += Ts[i][q] * G[q][j];
+            Ts[i][j] = -s_tau[j] * acc;
         }
     }
-#pragma unroll
-    for (int a = 0; a < kNB; ++a) ys[sl][a][cl] = y[a];
     __syncthreads();
-    if (sl != 0 || c >= nc) return;
 #pragma unroll
-    for (int a = 0; a < kNB; ++a) {
-        E t = E(0);
-#pragma unroll
-        for (int q = 0; q < kApplySlices; ++q) t += ys[q][a][cl];
-        y[a] = t;
-    }
-#pragma unroll
-    for (int a = 0; a < kNB; ++a) {
+    for (int h = 0; h < 2; ++h) {
+        const int e = tid + h * 1024;
+        const int a = e / 64, cl = e % 64;
+        const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+        if (c >= nc) continue;
         E z = E(0);
-#pragma unroll
-        for (int b2 = 0; b2 <= a; ++b2) z += Ts[b2 * kNB + a] * y[b2];
+        for (int b2 = 0; b2 <= a; ++b2) z += Ts[b2][a] * Y[b2][cl];
         Z[(int64_t)a * ldz + c] = z;
     }
 }
@@ -636,7 +649,6 @@ static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb)
     const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
     qb.Yp = ar.take<E>((size_t)nch * kNB * (size_t)ldo);
     qb.Z = ar.take<E>((size_t)kNB * (size_t)qb.ldw);
-    qb.T = ar.take<E>((size_t)kNB * kNB);
     qb.qtb = ar.take<E>((size_t)n);
     qb.RT = ar.take<E>((size_t)n * (size_t)n);
     qb.bar = ar.take<unsigned>(1024);
@@ -766,14 +778,11 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
         const int64_t chunk = chunk_rows(rows);
         const int nch = (int)ceil_div(rows, chunk);
         const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
-        hipLaunchKernelGGL(k_vtx_partial<E>, dim3(nch, 1), dim3(256), 0, s, rows, chunk, qb.V,
-                           (const E *)qb.V, (int64_t)kNB, (int64_t)kNB, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_form_t<E>, dim3(1), dim3(256), 0, s, nch, ldo, qb.Yp, qb.tau, p0, nbp, qb.T);
         const E *C0 = qb.W + p0 * ldw + c_first;
-        hipLaunchKernelGGL(k_vtx_partial<E>, dim3(nch, (unsigned)ceil_div(nc, 64)), dim3(256), 0, s,
-                           rows, chunk, qb.V, C0, ldw, nc, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_apply_t<E>, dim3((unsigned)ceil_div(nc, kApplyCols)), dim3(kApplyCols * kApplySlices), 0, s, nch, ldo,
-                           qb.Yp, qb.T, nc, qb.Z, ldw);
+        hipLaunchKernelGGL(k_vx_partial<E>, dim3(nch, (unsigned)ceil_div(kNB + nc, 64)), dim3(256), 0, s,
+                           rows, chunk, qb.V, C0, ldw, (int64_t)kNB + nc, ldo, qb.Yp);
+        hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, nch, ldo, qb.Yp,
+                           qb.tau, p0, nbp, nc, qb.Z, ldw);
         hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
                            dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);
     }

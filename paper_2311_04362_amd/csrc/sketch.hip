@@ -257,7 +257,33 @@ k_chunk_place(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ e
     __syncthreads();   // this work-group's entries are in place (visible to the work-group)
     for (int64_t k = threadIdx.x; k < d; k += blockDim.x) {
         const int32_t lo = b[k], hi = pos[k];
-        for (int32_t i = lo + 1; i < hi; ++i) {      // insertion sort by j of a few entries
+        if (hi - lo <= 1) continue;
+        if (hi - lo <= 16) {
+            // in registers: pad with the largest key (j <= 2^31 - 2), bitonic network, write back
+            uint32_t x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x[i] = (lo + i < hi) ? cols[lo + i] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int kk = 2; kk <= 16; kk <<= 1)
+#pragma unroll
+                for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int l = i ^ jj;
+                        if (l <= i) continue;
+                        const bool up = (i & kk) == 0;
+                        const uint32_t a = x[i], c = x[l];
+                        const bool swap = up ? ((a & 0x7FFFFFFFu) > (c & 0x7FFFFFFFu))
+                                             : ((a & 0x7FFFFFFFu) < (c & 0x7FFFFFFFu));
+                        x[i] = swap ? c : a;
+                        x[l] = swap ? a : c;
+                    }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (lo + i < hi) cols[lo + i] = x[i];
+            continue;
+        }
+        for (int32_t i = lo + 1; i < hi; ++i) {      // longer segments: insertion sort by j
             const uint32_t x = cols[i];
             int32_t q = i - 1;
             while (q >= lo && (cols[q] & 0x7FFFFFFFu) > (x & 0x7FFFFFFFu)) {
