@@ -10,8 +10,8 @@
 //
 // After the panel, the compact-WY form Q_p = I - V T V^T (T upper triangular) is built and the
 // trailing columns -- including the S b column, so Q is never formed -- are updated as
-// C <- C - V (T^T (V^T C)) by three launches: V^T [V | C] over row chunks (k_vx_partial), the chunk
-// sums with T and Z = T^T V^T C (k_tz), and C -= V Z (k_update_c).  Both products run on the matrix
+// C <- C - V (T^T (V^T C)) by four launches: V^T [V | C] over row chunks (k_vx_partial), the chunk
+// sums (k_sum_partials), T and Z = T^T V^T C (k_tz), and C -= V Z (k_update_c).  Both products run on the matrix
 // cores (v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 for the single-precision factorization of
 // the mixed-precision path); every reduction has a fixed order, so the factorization is
 // deterministic.  Every kernel is instantiated for FP64 and FP32.
@@ -427,19 +427,25 @@ k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__re
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) acc[h][sb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
-    for (int64_t r = r_lo + 4 * wave; r < r_hi; r += 16) {
-        const int64_t rr = r + kk;
-        const bool ok = rr < r_hi;
-        const E a0 = ok ? V[rr * kNB + ii] : E(0);
-        const E a1 = ok ? V[rr * kNB + 16 + ii] : E(0);
-        E bv[4];
+    // Rows r, r + 16, r + 32, r + 48 of this wave are loaded together, then applied in that order.
+    for (int64_t r = r_lo + 4 * wave; r < r_hi; r += 64) {
+        E a0[4], a1[4], bv[4][4];
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb) bv[sb] = (ok && cok[sb]) ? src[sb][rr * lds[sb]] : E(0);
+        for (int u = 0; u < 4; ++u) {
+            const int64_t rr = r + 16 * u + kk;
+            const bool ok = rr < r_hi;
+            a0[u] = ok ? V[rr * kNB + ii] : E(0);
+            a1[u] = ok ? V[rr * kNB + 16 + ii] : E(0);
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb) {
-            acc[0][sb] = Mfma<E>::mma(a0, bv[sb], acc[0][sb]);
-            acc[1][sb] = Mfma<E>::mma(a1, bv[sb], acc[1][sb]);
+            for (int sb = 0; sb < 4; ++sb) bv[u][sb] = (ok && cok[sb]) ? src[sb][rr * lds[sb]] : E(0);
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) {
+                acc[0][sb] = Mfma<E>::mma(a0[u], bv[u][sb], acc[0][sb]);
+                acc[1][sb] = Mfma<E>::mma(a1[u], bv[u][sb], acc[1][sb]);
+            }
     }
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb)
@@ -459,6 +465,21 @@ k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__re
     }
 }
 
+// P[0][a][c] <- sum over chunks ch of P[ch][a][c], added in chunk order, for a < kNB, c < nx.
+// Work-group (64-column block, 4 rows of the 32): one entry per thread, so the chunk partials of a
+// panel are summed by many compute units at once.  Each thread reads its entry of every chunk
+// before writing the sum over chunk 0's.
+template <typename E>
+__global__ void __launch_bounds__(256)
+k_sum_partials(int nch, int64_t ldo, int64_t nx, E *__restrict__ P)
+{
+    const int a = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (c >= nx) return;
+    E *p = P + (int64_t)a * ldo + c;
+    p[0] = strided_sum<8>(p, nch, (int64_t)kNB * ldo);
+}
+
 // For one 64-column block of the trailing columns: G = V^T V and Y = V^T C are the chunk sums of P
 // (added in chunk order); T is the compact-WY factor, T[j][j] = tau_j and T[0:j, j] =
 // -tau_j T[0:j, 0:j] G[0:j, j], formed by every work-group in its first wave; then
@@ -476,16 +497,45 @@ k_tz(int nch, int64_t ldo, const E *__restrict__ P, const E *__restrict__ tau, i
     const int64_t pstride = (int64_t)kNB * ldo;
     if (tid < kNB) s_tau[tid] = (tid < nbp) ? tau[p0 + tid] : E(0);
     {
-        const int a = tid / kNB, c = tid % kNB;
-        G[a][c] = strided_sum<8>(P + (int64_t)a * ldo + c, nch, pstride);
-        Ts[a][c] = E(0);
-    }
+        // Three chunk sums per thread (one entry of G, two of Y), each added in ascending chunk
+        // order; their loads are interleaved so that 24 are in flight at a time.
+        const int ga = tid / kNB, gc = tid % kNB;
+        const E *pg = P + (int64_t)ga * ldo + gc;
+        const E *py[2];
+        bool yok[2];
+        int ya[2], ycl[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = tid + h * 1024;
-        const int a = e / 64, cl = e % 64;
-        const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-        Y[a][cl] = (c < nc) ? strided_sum<8>(P + (int64_t)a * ldo + kNB + c, nch, pstride) : E(0);
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + h * 1024;
+            ya[h] = e / 64;
+            ycl[h] = e % 64;
+            const int64_t c = (int64_t)blockIdx.x * 64 + ycl[h];
+            yok[h] = c < nc;
+            py[h] = P + (int64_t)ya[h] * ldo + kNB + (yok[h] ? c : 0);
+        }
+        E g = E(0), y[2] = {E(0), E(0)};
+        for (int c0 = 0; c0 < nch; c0 += 8) {
+            E vg[8], vy[2][8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = c0 + u < nch;
+                const int64_t off = (int64_t)(c0 + u) * pstride;
+                vg[u] = in ? pg[off] : E(0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) vy[h][u] = (in && yok[h]) ? py[h][off] : E(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (c0 + u >= nch) break;
+                g += vg[u];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) y[h] += vy[h][u];
+            }
+        }
+        G[ga][gc] = g;
+        Ts[ga][gc] = E(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) Y[ya[h]][ycl[h]] = y[h];
     }
     __syncthreads();
     // Row i of T needs only its own earlier entries: T[i][j] = -tau_j sum_{q=i}^{j-1} T[i][q] G[q][j],
@@ -526,6 +576,17 @@ k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restric
     const int kk = lane >> 4, ii = lane & 15;
     const int64_t ra = r0 + ii;
     const bool ra_ok = ra < rows;
+    // this lane's 16 entries of C, loaded first so that their latency overlaps the products
+    E cv[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int64_t cc = c0 + 16 * cb + ii;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = r0 + Mfma<E>::row(q, lane);
+            cv[cb][q] = (cc < nc && r < rows) ? C[r * ldc + cc] : E(0);
+        }
+    }
     typename Mfma<E>::v4 acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
@@ -546,7 +607,7 @@ k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restric
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t r = r0 + Mfma<E>::row(q, lane);
-            if (r < rows) C[r * ldc + cc] -= acc[cb][q];
+            if (r < rows) C[r * ldc + cc] = cv[cb][q] - acc[cb][q];
         }
     }
 }
@@ -734,16 +795,14 @@ template <typename E>
 bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb,
                        int32_t *status, hipError_t &err)
 {
+    // One row per thread, as in k_panel_step: the work-groups' partial sums are then grouped exactly
+    // as the per-column path groups them, so the two paths give the same bits.  A grid too large
+    // to be co-resident takes the per-column path.
     const int64_t rows = d - p0;
     err = hipSuccess;
-    int nwg = (int)ceil_div(rows, kRB);
+    const int nwg = (int)ceil_div(rows, kRB);
     if (nwg <= coop_capacity<E, 1>()) {
         err = launch_panel_coop<E, 1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
-        return true;
-    }
-    nwg = (int)ceil_div(rows, 2 * kRB);
-    if (nwg <= coop_capacity<E, 2>()) {
-        err = launch_panel_coop<E, 2>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
         return true;
     }
     return false;
@@ -781,7 +840,9 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
         const E *C0 = qb.W + p0 * ldw + c_first;
         hipLaunchKernelGGL(k_vx_partial<E>, dim3(nch, (unsigned)ceil_div(kNB + nc, 64)), dim3(256), 0, s,
                            rows, chunk, qb.V, C0, ldw, (int64_t)kNB + nc, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, nch, ldo, qb.Yp,
+        hipLaunchKernelGGL(k_sum_partials<E>, dim3((unsigned)ceil_div(kNB + nc, 64), kNB / 4), dim3(256), 0, s,
+                           nch, ldo, (int64_t)kNB + nc, qb.Yp);
+        hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, 1, ldo, qb.Yp,
                            qb.tau, p0, nbp, nc, qb.Z, ldw);
         hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
                            dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);

@@ -188,7 +188,7 @@ k_csr_sort(int64_t d, const int32_t *__restrict__ rowptr, uint32_t *__restrict__
 // nonzeros in their segments (LDS counters) and sorts each segment, a handful of entries, by j.
 // Segments of one row follow chunk order, so every row ends in ascending j: the CSR of k_csr_sort.
 constexpr int kChunkCols = 8192;
-constexpr int64_t kLdsRows = 32768;
+constexpr int64_t kLdsRows = 40960;      // 160 KiB of int32 counters
 
 __global__ void __launch_bounds__(1024)
 k_chunk_hist(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ ent,
