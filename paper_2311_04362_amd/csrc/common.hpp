@@ -117,7 +117,7 @@ struct SketchBufs {
     int32_t *rowptr;     // d+1
     int32_t *fill;       // d
     uint32_t *cols;      // m*zeta packed (j | sign<<31), by sketch row, ascending j
-    int32_t *chunk_cnt;  // ceil(m / 8192) x d per-chunk row counts (d <= 40960, at most 2^26), else nullptr
+    int32_t *chunk_cnt;  // ceil(m / 8192) x d per-chunk row counts (8192 zeta / 8 <= d <= 40960), else nullptr
     WinLists win;        // built by launch_csr when active
 };
 // n > 0 and win_mode == 0: also carve the lists of the column-sliced gather when the shape suits it.

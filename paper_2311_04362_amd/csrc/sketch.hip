@@ -549,8 +549,12 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
     sb.rowptr = ar.take<int32_t>((size_t)d + 1);
     sb.fill = ar.take<int32_t>((size_t)d);
     sb.cols = ar.take<uint32_t>(nnz);
+    // The chunk path needs the counters in LDS (d <= kLdsRows), short segments (a (chunk, row)
+    // segment holds kChunkCols zeta / d entries on average: at most 8, so the register sort takes
+    // nearly all of them) and a bounded count matrix.
     const size_t chunk_cells = (size_t)((m + kChunkCols - 1) / kChunkCols) * (size_t)d;
-    sb.chunk_cnt = (d <= kLdsRows && chunk_cells <= ((size_t)1 << 26)) ? ar.take<int32_t>(chunk_cells) : nullptr;
+    const bool chunk_path = d <= kLdsRows && 8 * d >= (int64_t)kChunkCols * zeta && chunk_cells <= ((size_t)1 << 26);
+    sb.chunk_cnt = chunk_path ? ar.take<int32_t>(chunk_cells) : nullptr;
     sb.win = WinLists{};
     // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
     // slices keep the eight XCDs busy and A is large.

@@ -62,7 +62,11 @@ def test_embedding_bit_exact(ctx, m, d, zeta, seed):
 
 @pytest.mark.parametrize("m,d,zeta,seed", [(4000, 1000, 8, 4), (1000, 3, 1, 2), (777, 50, 8, 3),
                                            (40000, 4, 2, 5),      # 20000-entry rows: global-memory sort
-                                           (200000, 10000, 8, 11)])
+                                           (200000, 10000, 8, 11),
+                                           (100000, 40960, 8, 6),  # largest d of the chunked CSR
+                                           (100000, 40961, 8, 6),  # past it: atomic CSR
+                                           (20000, 8192, 8, 7),    # smallest d of the chunked CSR
+                                           (20000, 8191, 8, 7)])   # below it: atomic CSR
 def test_csr_bit_exact(ctx, m, d, zeta, seed):
     rowptr, cols = ctx.sketch_csr(m, d, zeta, seed)
     erp, ec = expected_csr(m, d, zeta, seed)
