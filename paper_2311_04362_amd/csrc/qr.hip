@@ -59,16 +59,22 @@ __device__ __forceinline__ E wave_transpose_sum(E (&v)[kNB], int lane)
 #pragma unroll
     for (int half = kNB / 2, off = 32; half >= 1; half >>= 1, off >>= 1) {
         const bool upper = (lane & off) != 0;
+        E send[kNB / 2], keep[kNB / 2], recv[kNB / 2];
+        // A stage selects all its values first, then exchanges them all, then adds: the exchanges
+        // of a stage are in flight together (one wait per stage, not one per value).  The empty
+        // asm keeps each pair opaque: otherwise the compiler folds the selects into one load with
+        // a lane-dependent index, which moves v to scratch memory.
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            // The empty asm keeps the two values opaque: otherwise the compiler folds the selects
-            // below into one load with a lane-dependent index, which moves v to scratch memory.
             E lo = v[i], hi = v[i + half];
             asm volatile("" : "+v"(lo), "+v"(hi));
-            const E send = upper ? lo : hi;
-            const E keep = upper ? hi : lo;
-            v[i] = keep + __shfl_xor(send, off, 64);
+            send[i] = upper ? lo : hi;
+            keep[i] = upper ? hi : lo;
         }
+#pragma unroll
+        for (int i = 0; i < half; ++i) recv[i] = __shfl_xor(send[i], off, 64);
+#pragma unroll
+        for (int i = 0; i < half; ++i) v[i] = keep[i] + recv[i];
     }
     return v[0] + __shfl_xor(v[0], 1, 64);
 }
