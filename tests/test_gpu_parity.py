@@ -198,8 +198,8 @@ def test_gradient_integer_exact(ctx, n):
 @pytest.mark.parametrize("n", NS)
 @pytest.mark.parametrize("m", [1, 3, 4099, 100003])
 def test_gradient_float_bound(ctx, n, m):
-    if m * n > 60_000_000:
-        pytest.skip("oracle time")
+    if m * n > 60_000_000:          # keep the oracle's work bounded: the largest odd m that fits
+        m = (60_000_000 // n) | 1
     rng = np.random.default_rng(n * 31 + m)
     A = rng.standard_normal((m, n))
     x = rng.standard_normal(n)
