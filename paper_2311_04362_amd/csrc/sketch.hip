@@ -368,7 +368,7 @@ constexpr int kWinWaves = 16;          // waves per work-group (one group of rw 
 constexpr int kWinMaxRows = 20;        // rw at most: 16 x 20 x 64 doubles = 160 KiB of LDS
 constexpr int64_t kWinLen = 4096;      // rows of A per list window
 constexpr int kWinPerStep = 4;         // windows between two work-group barriers
-constexpr int kWinBatch = 16;          // rows of A in flight per wave
+constexpr int kWinBatch = 8;           // rows of A in flight per wave (16 in flight fetch 1.8x the bytes)
 
 // ctab[w*d + k] = entries of sketch row k in windows < w, for w = 0..nwl: entry p of the row
 // writes the windows (window of entry p-1, window of entry p], and p = L closes up to nwl, so every
