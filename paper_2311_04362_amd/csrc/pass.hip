@@ -234,7 +234,10 @@ PassVariant pass_variant(int64_t n)
     return {pass_fn<64, 32, 1>(), 8};
 }
 
-// Work-groups that fit on the device at once for a variant (cached per device and variant).
+// Work-groups that fit on the device at once for a variant (cached per device and variant).  The
+// 257..512-column variant (id 6) takes one work-group per CU instead: with fewer row streams open at
+// once it reads A at 7.1 TB/s, against 7.0 TB/s with all three that fit.  The variant for 2000
+// columns measured faster with every resident work-group, so the others keep the full count.
 int resident_wgs(int id, const void *fn)
 {
     static int cache[64][9];
@@ -248,6 +251,7 @@ int resident_wgs(int id, const void *fn)
         (void)hipGetLastError();
         return 256;
     }
+    if (id == 6) per_cu = 1;
     cache[dev][id] = cus * per_cu;
     return cache[dev][id];
 }
@@ -306,7 +310,7 @@ hipError_t launch_served_reduce(hipStream_t s, int total_wg, const ServeSlot *sl
 
 int32_t iter_partials(int64_t m, int64_t n)
 {
-    // One wave of co-resident work-groups (at most one per 256 rows).
+    // One wave of co-resident work-groups (at most one per 256 rows), or one per CU (id 6).
     const PassVariant v = pass_variant(n);
     int64_t P = resident_wgs(v.id, v.fn);
     if (P > kMaxPartials) P = kMaxPartials;
