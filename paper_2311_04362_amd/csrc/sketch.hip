@@ -5,21 +5,23 @@
 //   k_scan_rows     exclusive scan of the row histogram -> CSR row pointers.
 //   k_csr_scatter   places each nonzero in its sketch row (slot order within a row is arbitrary).
 //   k_csr_sort      sorts every sketch row by column index j, making the CSR unique: ascending j.
-//   k_chunk_*       the same CSR for d <= kLdsRows from per-chunk LDS histograms, without global
-//                   atomics and without the row sort (below); k_sparse_sign then skips its histogram.
+//   k_chunk_*       the same CSR from per-chunk LDS histograms, without global atomics and without
+//                   the row sort, when d <= kLdsRows and the (chunk, row) segments are short (below);
+//                   k_sparse_sign then skips its histogram.
 //   k_gather        one wave per (sketch row, 64*CPL-column tile): B[k,:] = sum of +-A[j,:] over the
 //                   row's columns in ascending j, times fl(1/sqrt(zeta)).  Rows of A are read as
 //                   coalesced 512-byte segments (non-temporal); no atomics on floating-point data.
 //                   Every row of A is fetched from HBM once per nonzero of its column of S (zeta x).
 //   k_win_count, k_win_scan, k_win_scatter
 //                   reorder each group of sketch rows' CSR entries window by window (below).
-//   k_gather_win    the same sums with each row of A fetched from HBM about once: a work-group owns
-//                   a 64-column slice of 16*rw sketch rows, accumulated in LDS; the eight slices that
-//                   share rows of A run on the eight XCDs at the same time (one slice per XCD), and
-//                   a work-group barrier every kWinPerStep windows keeps the 16 waves of a CU within
-//                   a few thousand rows of A of each other, so the other nonzeros of a row of A
-//                   find it in that XCD's L2.  Each accumulator has one owner (its wave) and
-//                   receives its terms in ascending j, so the bits equal k_gather's.
+//   k_gather_win    the same sums with each row of A fetched from HBM once or twice, not zeta times:
+//                   a work-group owns a 64-column slice of 16*rw sketch rows, accumulated in LDS;
+//                   the eight slices that share rows of A run on the eight XCDs at the same time
+//                   (one slice per XCD), and a work-group barrier every kWinPerStep windows keeps
+//                   the 16 waves of a CU within a few thousand rows of A of each other, so the
+//                   other nonzeros of a row of A find it in that XCD's L2.  Each accumulator has one
+//                   owner (its wave) and receives its terms in ascending j, so the bits equal
+//                   k_gather's.
 #include "common.hpp"
 
 namespace {
