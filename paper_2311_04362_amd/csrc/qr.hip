@@ -50,16 +50,58 @@ template <> struct Mfma<float> {
 };
 
 
+// Exchanges between two registers across lane halves: with x, y on entry, lane l ends with
+// x = (own x, or the partner's y) and y = (the partner's x, or own y), the partner being l ^ 32
+// (v_permlane32_swap) or l ^ 16 (v_permlane16_swap), so x + y is what a lane of the lower half
+// (lane & off == 0) gets by adding its x to the partner's x, and a lane of the upper half by
+// adding its y to the partner's y.  (Lane layout of both instructions checked on gfx950.)
+template <bool k32>
+__device__ __forceinline__ void lane_swap(double &x, double &y)
+{
+    const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+    const unsigned alo = (unsigned)a, ahi = (unsigned)(a >> 32), blo = (unsigned)b, bhi = (unsigned)(b >> 32);
+    const auto lo = k32 ? __builtin_amdgcn_permlane32_swap(alo, blo, false, false)
+                        : __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto hi = k32 ? __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false)
+                        : __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    x = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[0] << 32) | (unsigned)lo[0]);
+    y = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[1] << 32) | (unsigned)lo[1]);
+}
+
+template <bool k32>
+__device__ __forceinline__ void lane_swap(float &x, float &y)
+{
+    const auto r = k32 ? __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y), false, false)
+                       : __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y), false, false);
+    x = __builtin_bit_cast(float, (unsigned)r[0]);
+    y = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
 // Sums v[0..kNB) across the 64 lanes of a wave by recursive halving: at each step a lane keeps half
-// of its values and adds the partner's copy of them, so 32 values need 16+8+4+2+1+1 exchanges.
+// of its values and adds the partner's copy of them (partner lane ^ 32, ^ 16, ..., ^ 1), so 32
+// values need 16+8+4+2+1+1 exchanges.  The first two steps, which carry 24 of the 31 exchanges, are
+// register swaps on the VALU (lane_swap); the rest go through ds_bpermute.
 // On return lane l holds the wave total of value (l >> 1) & 31 (both lanes of a pair agree).
 template <typename E>
 __device__ __forceinline__ E wave_transpose_sum(E (&v)[kNB], int lane)
 {
+    static_assert(kNB == 32, "the swap steps take the partner offsets 32 and 16");
 #pragma unroll
-    for (int half = kNB / 2, off = 32; half >= 1; half >>= 1, off >>= 1) {
+    for (int i = 0; i < 16; ++i) {
+        E x = v[i], y = v[i + 16];
+        lane_swap<true>(x, y);
+        v[i] = x + y;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        E x = v[i], y = v[i + 8];
+        lane_swap<false>(x, y);
+        v[i] = x + y;
+    }
+#pragma unroll
+    for (int half = 4, off = 8; half >= 1; half >>= 1, off >>= 1) {
         const bool upper = (lane & off) != 0;
-        E send[kNB / 2], keep[kNB / 2], recv[kNB / 2];
+        E send[4], keep[4], recv[4];
         // A stage selects all its values first, then exchanges them all, then adds: the exchanges
         // of a stage are in flight together (one wait per stage, not one per value).  The empty
         // asm keeps each pair opaque: otherwise the compiler folds the selects into one load with
