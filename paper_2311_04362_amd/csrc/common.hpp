@@ -110,15 +110,21 @@ struct WinLists {
     int32_t *ctab = nullptr;   // (nwl+1) x d: entries of row k in windows < w
     int32_t *stab = nullptr;   // nwl x d: list offsets (k_win_scan)
     int32_t *woff = nullptr;   // groups x (nstep+1): where each barrier step starts in a list
+    // Lists built from the embedding without the CSR (k_wl_*; d <= 40960, short segments):
+    bool direct = false;
+    int32_t *cnt = nullptr;    // nwl x d: entries of row k in window w
+    int32_t *rel = nullptr;    // groups x nwl: entries of group g in window w, then their scan
+    int32_t *gtot = nullptr;   // groups: list length of each group
+    int32_t *gstart = nullptr; // groups + 1: where each group's list starts
 };
 struct SketchBufs {
-    uint32_t *ent;       // m*zeta packed (row | sign<<31), column-major by j
-    int32_t *rowcount;   // d
-    int32_t *rowptr;     // d+1
-    int32_t *fill;       // d
-    uint32_t *cols;      // m*zeta packed (j | sign<<31), by sketch row, ascending j
-    int32_t *chunk_cnt;  // ceil(m / 8192) x d per-chunk row counts (8192 zeta / 8 <= d <= 40960), else nullptr
-    WinLists win;        // built by launch_csr when active
+    uint32_t *ent = nullptr;       // m*zeta packed (row | sign<<31), column-major by j
+    int32_t *rowcount = nullptr;   // d
+    int32_t *rowptr = nullptr;     // d+1
+    int32_t *fill = nullptr;       // d
+    uint32_t *cols = nullptr;      // m*zeta packed (j | sign<<31), by sketch row, ascending j (null when win.direct)
+    int32_t *chunk_cnt = nullptr;  // ceil(m / 8192) x d per-chunk row counts (8192 zeta / 8 <= d <= 40960), else null
+    WinLists win;        // built by launch_csr when active (without the CSR when win.direct)
 };
 // n > 0 and win_mode == 0: also carve the lists of the column-sliced gather when the shape suits it.
 void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, int64_t n = 0,

@@ -448,6 +448,140 @@ k_win_scatter(int64_t d, const int32_t *__restrict__ rowptr, const uint32_t *__r
     }
 }
 
+// ---- window lists straight from the embedding (d <= kLdsRows, short segments) --------------------
+// Window w of the lists is columns [w kWinLen, (w+1) kWinLen) of S, i.e. a contiguous range of the
+// embedding, so the lists can be built without the CSR: a row histogram per window, a scan over the
+// windows of each group, a scan over the groups, then each window places its entries in their
+// (group, window) segments by LDS counters and sorts every (window, row) segment by j.  The lists
+// equal those of k_win_count / k_win_scan / k_win_scatter entry for entry.
+
+// cnt[w][k] = entries of sketch row k in window w; tot[g][w] = entries of group g in window w.
+template <int RW>
+__global__ void __launch_bounds__(1024)
+k_wl_hist(int64_t m, int64_t d, int32_t zeta, int32_t nwl, const uint32_t *__restrict__ ent,
+          int32_t *__restrict__ cnt, int32_t *__restrict__ tot)
+{
+    __shared__ int32_t h[kLdsRows];
+    const int64_t w = blockIdx.x;
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const int64_t j1 = ((w + 1) * kWinLen < m) ? (w + 1) * kWinLen : m;
+    for (int64_t i = w * kWinLen * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x)
+        atomicAdd(&h[ent[i] & 0x7FFFFFFFu], 1);
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) cnt[w * d + k] = h[k];
+    const int64_t ngroups = (d + RW - 1) / RW;
+    for (int64_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+        int32_t t = 0;
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+            if (g * RW + r < d) t += h[g * RW + r];
+        tot[g * nwl + w] = t;
+    }
+}
+
+// One wave per group: tot[g][:] becomes its exclusive scan over the windows (the group-relative
+// start of each window's segment), and gtot[g] the group's length.
+__global__ void __launch_bounds__(256)
+k_wl_wscan(int64_t ngroups, int32_t nwl, int32_t *__restrict__ tot, int32_t *__restrict__ gtot)
+{
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= ngroups) return;
+    int32_t *t = tot + g * nwl;
+    int32_t carry = 0;
+    for (int32_t w0 = 0; w0 < nwl; w0 += 64) {
+        const int32_t w = w0 + lane;
+        const int32_t v = (w < nwl) ? t[w] : 0;
+        int32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (w < nwl) t[w] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) gtot[g] = carry;
+}
+
+// Window w places its entries: row k's entries of the window go to gstart[g] + rel[g][w] plus the
+// entries of the group's earlier rows in the window; the window also records where its barrier
+// step starts in each group's list (woff).  Each (window, row) segment is then sorted by j.
+template <int RW>
+__global__ void __launch_bounds__(1024)
+k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
+           const uint32_t *__restrict__ ent, const int32_t *__restrict__ cnt,
+           const int32_t *__restrict__ rel, const int32_t *__restrict__ gstart,
+           const int32_t *__restrict__ gtot, int32_t *__restrict__ woff, uint32_t *__restrict__ lst,
+           uint8_t *__restrict__ rloc)
+{
+    __shared__ int32_t h[kLdsRows];
+    const int64_t w = blockIdx.x;
+    const int64_t ngroups = (d + RW - 1) / RW;
+    const int32_t *c = cnt + w * d;
+    for (int64_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+        int32_t run = gstart[g] + rel[g * nwl + w];
+        if (w % kWinPerStep == 0) woff[g * (nstep + 1) + w / kWinPerStep] = run;
+        if (w == nwl - 1) woff[g * (nstep + 1) + nstep] = gstart[g] + gtot[g];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int64_t k = g * RW + r;
+            if (k < d) {
+                h[k] = run;
+                run += c[k];
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t j1 = ((w + 1) * kWinLen < m) ? (w + 1) * kWinLen : m;
+    for (int64_t i = w * kWinLen * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x) {
+        const uint32_t v = ent[i];
+        const uint32_t k = v & 0x7FFFFFFFu;
+        const int32_t p = atomicAdd(&h[k], 1);
+        lst[p] = (uint32_t)(i / zeta) | (v & 0x80000000u);
+        rloc[p] = (uint8_t)(k % RW);
+    }
+    __syncthreads();   // this work-group's entries are in place (visible to the work-group)
+    for (int64_t k = threadIdx.x; k < d; k += blockDim.x) {
+        const int32_t hi = h[k], lo = hi - c[k];
+        if (hi - lo <= 1) continue;
+        if (hi - lo <= 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x[i] = (lo + i < hi) ? lst[lo + i] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int kk = 2; kk <= 16; kk <<= 1)
+#pragma unroll
+                for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int l = i ^ jj;
+                        if (l <= i) continue;
+                        const bool up = (i & kk) == 0;
+                        const uint32_t a = x[i], b = x[l];
+                        const bool swap = up ? ((a & 0x7FFFFFFFu) > (b & 0x7FFFFFFFu))
+                                             : ((a & 0x7FFFFFFFu) < (b & 0x7FFFFFFFu));
+                        x[i] = swap ? b : a;
+                        x[l] = swap ? a : b;
+                    }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (lo + i < hi) lst[lo + i] = x[i];
+            continue;
+        }
+        for (int32_t i = lo + 1; i < hi; ++i) {      // longer segments: insertion sort by j
+            const uint32_t x = lst[i];
+            int32_t q = i - 1;
+            while (q >= lo && (lst[q] & 0x7FFFFFFFu) > (x & 0x7FFFFFFFu)) {
+                lst[q + 1] = lst[q];
+                --q;
+            }
+            lst[q + 1] = x;
+        }
+    }
+}
+
 // Work-group (XCD x = blockIdx % 8, block blockIdx / 8) takes column slice slice0 + x and row block
 // rb0 + blockIdx / 8 (16 groups of RW sketch rows, one per wave).  Lane l of a wave owns column
 // 64*slice + l of its RW rows in LDS; column n is S b (lane reads b).  The wave walks its group's
@@ -546,10 +680,40 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
                  int32_t win_mode)
 {
     const size_t nnz = (size_t)m * (size_t)zeta;
+    sb = SketchBufs{};
     sb.ent = ar.take<uint32_t>(nnz);
     sb.rowcount = ar.take<int32_t>((size_t)d);
     sb.rowptr = ar.take<int32_t>((size_t)d + 1);
     sb.fill = ar.take<int32_t>((size_t)d);
+    // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
+    // slices keep the eight XCDs busy and A is large.
+    const int cus = (win_mode == 0 && n >= 448 && m >= 65536 && d >= 64) ? cus_per_xcd() : 0;
+    WinLists &w = sb.win;
+    if (cus > 0) {
+        w.active = true;
+        w.cus = cus;
+        w.rw = win_rows(d, cus);
+        w.nwl = (int32_t)((m + kWinLen - 1) / kWinLen);
+        w.nstep = (w.nwl + kWinPerStep - 1) / kWinPerStep;
+        const int64_t ngroups = (d + w.rw - 1) / w.rw;
+        w.lst = ar.take<uint32_t>(nnz);
+        w.rloc = ar.take<uint8_t>(nnz);
+        w.woff = ar.take<int32_t>((size_t)ngroups * (size_t)(w.nstep + 1));
+        // Straight from the embedding, with no CSR at all, when the row counters fit in LDS, a
+        // (window, row) segment holds kWinLen zeta / d <= 8 entries on average (the register sort
+        // takes nearly all of them) and the count matrix is bounded.
+        const size_t win_cells = (size_t)w.nwl * (size_t)d;
+        w.direct = d <= kLdsRows && 8 * d >= kWinLen * zeta && win_cells <= ((size_t)1 << 26);
+        if (w.direct) {
+            w.cnt = ar.take<int32_t>(win_cells);
+            w.rel = ar.take<int32_t>((size_t)ngroups * (size_t)w.nwl);
+            w.gtot = ar.take<int32_t>((size_t)ngroups);
+            w.gstart = ar.take<int32_t>((size_t)ngroups + 1);
+            return;                                   // sb.cols and sb.chunk_cnt stay null
+        }
+        w.ctab = ar.take<int32_t>((size_t)(w.nwl + 1) * (size_t)d);
+        w.stab = ar.take<int32_t>((size_t)w.nwl * (size_t)d);
+    }
     sb.cols = ar.take<uint32_t>(nnz);
     // The chunk path needs the counters in LDS (d <= kLdsRows), short segments (a (chunk, row)
     // segment holds kChunkCols zeta / d entries on average: at most 8, so the register sort takes
@@ -557,30 +721,13 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
     const size_t chunk_cells = (size_t)((m + kChunkCols - 1) / kChunkCols) * (size_t)d;
     const bool chunk_path = d <= kLdsRows && 8 * d >= (int64_t)kChunkCols * zeta && chunk_cells <= ((size_t)1 << 26);
     sb.chunk_cnt = chunk_path ? ar.take<int32_t>(chunk_cells) : nullptr;
-    sb.win = WinLists{};
-    // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
-    // slices keep the eight XCDs busy and A is large.
-    const int cus = (win_mode == 0 && n >= 448 && m >= 65536 && d >= 64) ? cus_per_xcd() : 0;
-    if (cus == 0) return;
-    WinLists &w = sb.win;
-    w.active = true;
-    w.cus = cus;
-    w.rw = win_rows(d, cus);
-    w.nwl = (int32_t)((m + kWinLen - 1) / kWinLen);
-    w.nstep = (w.nwl + kWinPerStep - 1) / kWinPerStep;
-    const int64_t ngroups = (d + w.rw - 1) / w.rw;
-    w.lst = ar.take<uint32_t>(nnz);
-    w.rloc = ar.take<uint8_t>(nnz);
-    w.ctab = ar.take<int32_t>((size_t)(w.nwl + 1) * (size_t)d);
-    w.stab = ar.take<int32_t>((size_t)w.nwl * (size_t)d);
-    w.woff = ar.take<int32_t>((size_t)ngroups * (size_t)(w.nstep + 1));
 }
 
 hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
                               const SketchBufs &sb)
 {
-    int32_t *count = nullptr;          // the chunk path counts rows itself, without global atomics
-    if (!sb.chunk_cnt) {
+    int32_t *count = nullptr;          // the chunk and direct paths count rows themselves
+    if (!sb.chunk_cnt && !sb.win.direct) {
         hipError_t e = hipMemsetAsync(sb.rowcount, 0, sizeof(int32_t) * (size_t)d, s);
         if (e != hipSuccess) return e;
         count = sb.rowcount;
@@ -601,6 +748,26 @@ hipError_t launch_unpack_embedding(hipStream_t s, int64_t m, int32_t zeta, const
 hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const SketchBufs &sb)
 {
     const int64_t nnz = m * zeta;
+    if (sb.win.active && sb.win.direct) {            // the gather's lists only, no CSR
+        const WinLists &w = sb.win;
+        const int64_t ngroups = (d + w.rw - 1) / w.rw;
+        switch (w.rw) {
+#define LS_WL_CASE(R)                                                                                     \
+        case R:                                                                                           \
+            hipLaunchKernelGGL(k_wl_hist<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta, w.nwl,   \
+                               sb.ent, w.cnt, w.rel);                                                     \
+            hipLaunchKernelGGL(k_wl_wscan, dim3(blocks_for(ngroups, 4)), dim3(256), 0, s, ngroups, w.nwl,  \
+                               w.rel, w.gtot);                                                            \
+            hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, ngroups, w.gtot, w.gstart, sb.fill); \
+            hipLaunchKernelGGL(k_wl_place<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta, w.nwl,  \
+                               w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst, w.rloc);   \
+            break;
+        LS_WL_CASE(4) LS_WL_CASE(8) LS_WL_CASE(12) LS_WL_CASE(16) LS_WL_CASE(20)
+#undef LS_WL_CASE
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (sb.chunk_cnt) {
         const int32_t nchunk = (int32_t)((m + kChunkCols - 1) / kChunkCols);
         hipLaunchKernelGGL(k_chunk_hist, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, sb.ent, sb.chunk_cnt);
