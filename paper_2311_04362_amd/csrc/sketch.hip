@@ -371,6 +371,11 @@ constexpr int kWinMaxRows = 20;        // rw at most: 16 x 20 x 64 doubles = 160
 constexpr int64_t kWinLen = 4096;      // rows of A per list window
 constexpr int kWinPerStep = 4;         // windows between two work-group barriers
 constexpr int kWinBatch = 8;           // rows of A in flight per wave (16 in flight fetch 1.8x the bytes)
+// A list entry packs the column j of S (bits 0..25), the entry's row within its group (26..30) and
+// the sign (31), so the column-sliced gather takes m < 2^26.
+constexpr int kListJBits = 26;
+constexpr uint32_t kListJMask = (1u << kListJBits) - 1u;
+constexpr int64_t kListMaxRows = (int64_t)1 << kListJBits;
 
 // ctab[w*d + k] = entries of sketch row k in windows < w, for w = 0..nwl: entry p of the row
 // writes the windows (window of entry p-1, window of entry p], and p = L closes up to nwl, so every
@@ -427,11 +432,11 @@ k_win_scan(int64_t d, int32_t nwl, int32_t nstep, const int32_t *__restrict__ ro
     }
 }
 
-// Places every CSR entry in its group's list; rloc records its row within the group.
+// Places every CSR entry in its group's list, with its row within the group packed in.
 template <int RW>
 __global__ void __launch_bounds__(256)
 k_win_scatter(int64_t d, const int32_t *__restrict__ rowptr, const uint32_t *__restrict__ cols,
-              const int32_t *__restrict__ stab, uint32_t *__restrict__ lst, uint8_t *__restrict__ rloc)
+              const int32_t *__restrict__ stab, uint32_t *__restrict__ lst)
 {
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -443,8 +448,7 @@ k_win_scatter(int64_t d, const int32_t *__restrict__ rowptr, const uint32_t *__r
         const uint32_t v = cols[lo + p];
         const int32_t w = (int32_t)((v & 0x7FFFFFFFu) / kWinLen);
         const int32_t dst = gs + p + stab[(int64_t)w * d + k];
-        lst[dst] = v;
-        rloc[dst] = (uint8_t)(k - g * RW);
+        lst[dst] = v | ((uint32_t)(k - g * RW) << kListJBits);
     }
 }
 
@@ -513,8 +517,7 @@ __global__ void __launch_bounds__(1024)
 k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
            const uint32_t *__restrict__ ent, const int32_t *__restrict__ cnt,
            const int32_t *__restrict__ rel, const int32_t *__restrict__ gstart,
-           const int32_t *__restrict__ gtot, int32_t *__restrict__ woff, uint32_t *__restrict__ lst,
-           uint8_t *__restrict__ rloc)
+           const int32_t *__restrict__ gtot, int32_t *__restrict__ woff, uint32_t *__restrict__ lst)
 {
     __shared__ int32_t h[kLdsRows];
     const int64_t w = blockIdx.x;
@@ -539,8 +542,7 @@ k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
         const uint32_t v = ent[i];
         const uint32_t k = v & 0x7FFFFFFFu;
         const int32_t p = atomicAdd(&h[k], 1);
-        lst[p] = (uint32_t)(i / zeta) | (v & 0x80000000u);
-        rloc[p] = (uint8_t)(k % RW);
+        lst[p] = (uint32_t)(i / zeta) | ((k % RW) << kListJBits) | (v & 0x80000000u);
     }
     __syncthreads();   // this work-group's entries are in place (visible to the work-group)
     for (int64_t k = threadIdx.x; k < d; k += blockDim.x) {
@@ -560,8 +562,8 @@ k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
                         if (l <= i) continue;
                         const bool up = (i & kk) == 0;
                         const uint32_t a = x[i], b = x[l];
-                        const bool swap = up ? ((a & 0x7FFFFFFFu) > (b & 0x7FFFFFFFu))
-                                             : ((a & 0x7FFFFFFFu) < (b & 0x7FFFFFFFu));
+                        const bool swap = up ? ((a & kListJMask) > (b & kListJMask))
+                                             : ((a & kListJMask) < (b & kListJMask));
                         x[i] = swap ? b : a;
                         x[l] = swap ? a : b;
                     }
@@ -573,7 +575,7 @@ k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
         for (int32_t i = lo + 1; i < hi; ++i) {      // longer segments: insertion sort by j
             const uint32_t x = lst[i];
             int32_t q = i - 1;
-            while (q >= lo && (lst[q] & 0x7FFFFFFFu) > (x & 0x7FFFFFFFu)) {
+            while (q >= lo && (lst[q] & kListJMask) > (x & kListJMask)) {
                 lst[q + 1] = lst[q];
                 --q;
             }
@@ -593,7 +595,7 @@ __global__ void __launch_bounds__(kWinWaves * 64)
 k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0,
              const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
              const int32_t *__restrict__ woff, int32_t nstep, const uint32_t *__restrict__ lst,
-             const uint8_t *__restrict__ rloc, double scale, OT *__restrict__ B, int64_t ldb,
+             double scale, OT *__restrict__ B, int64_t ldb,
              OT *__restrict__ Sb, int64_t ldsb)
 {
     __shared__ double acc[kWinWaves * kWinMaxRows * 64];   // full size: one work-group per CU
@@ -621,7 +623,6 @@ k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0,
         for (int32_t e0 = lo; e0 < hi; e0 += 64) {
             const int cnt = (hi - e0 < 64) ? hi - e0 : 64;
             const uint32_t vd = lane < cnt ? lst[e0 + lane] : 0u;
-            const int rd = lane < cnt ? (int)rloc[e0 + lane] : 0;
             int u0 = 0;
             for (; u0 + kWinBatch <= cnt; u0 += kWinBatch) {
                 uint32_t v[kWinBatch];
@@ -629,18 +630,18 @@ k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0,
 #pragma unroll
                 for (int u = 0; u < kWinBatch; ++u) {
                     v[u] = __builtin_amdgcn_readlane(vd, u0 + u);
-                    a[u] = src[(int64_t)(v[u] & 0x7FFFFFFFu) * stride];
+                    a[u] = src[(int64_t)(v[u] & kListJMask) * stride];
                 }
 #pragma unroll
                 for (int u = 0; u < kWinBatch; ++u) {
-                    const int r = __builtin_amdgcn_readlane(rd, u0 + u);
+                    const int r = (int)((v[u] >> kListJBits) & 31u);
                     atomicAdd(my + r * 64, (v[u] >> 31) ? -a[u] : a[u]);
                 }
             }
             for (; u0 < cnt; ++u0) {
                 const uint32_t v = __builtin_amdgcn_readlane(vd, u0);
-                const int r = __builtin_amdgcn_readlane(rd, u0);
-                const double a = src[(int64_t)(v & 0x7FFFFFFFu) * stride];
+                const int r = (int)((v >> kListJBits) & 31u);
+                const double a = src[(int64_t)(v & kListJMask) * stride];
                 atomicAdd(my + r * 64, (v >> 31) ? -a : a);
             }
         }
@@ -687,7 +688,7 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
     sb.fill = ar.take<int32_t>((size_t)d);
     // The column-sliced gather pays for its lists and its fixed grid when at least seven 64-column
     // slices keep the eight XCDs busy and A is large.
-    const int cus = (win_mode == 0 && n >= 448 && m >= 65536 && d >= 64) ? cus_per_xcd() : 0;
+    const int cus = (win_mode == 0 && n >= 448 && m >= 65536 && m < kListMaxRows && d >= 64) ? cus_per_xcd() : 0;
     WinLists &w = sb.win;
     if (cus > 0) {
         w.active = true;
@@ -697,7 +698,6 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
         w.nstep = (w.nwl + kWinPerStep - 1) / kWinPerStep;
         const int64_t ngroups = (d + w.rw - 1) / w.rw;
         w.lst = ar.take<uint32_t>(nnz);
-        w.rloc = ar.take<uint8_t>(nnz);
         w.woff = ar.take<int32_t>((size_t)ngroups * (size_t)(w.nstep + 1));
         // Straight from the embedding, with no CSR at all, when the row counters fit in LDS, a
         // (window, row) segment holds kWinLen zeta / d <= 8 entries on average (the register sort
@@ -760,7 +760,7 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
                                w.rel, w.gtot);                                                            \
             hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, ngroups, w.gtot, w.gstart, sb.fill); \
             hipLaunchKernelGGL(k_wl_place<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta, w.nwl,  \
-                               w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst, w.rloc);   \
+                               w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst);           \
             break;
         LS_WL_CASE(4) LS_WL_CASE(8) LS_WL_CASE(12) LS_WL_CASE(16) LS_WL_CASE(20)
 #undef LS_WL_CASE
@@ -792,7 +792,7 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
         hipLaunchKernelGGL(k_win_scan<R>, dim3(pair_blocks), dim3(256), 0, s, d, w.nwl, w.nstep,        \
                            sb.rowptr, w.ctab, w.stab, w.woff);                                           \
         hipLaunchKernelGGL(k_win_scatter<R>, dim3(row_blocks), dim3(256), 0, s, d, sb.rowptr, sb.cols,   \
-                           w.stab, w.lst, w.rloc);                                                       \
+                           w.stab, w.lst);                                                               \
         break;
     LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
 #undef LS_WIN_CASE
@@ -822,7 +822,7 @@ hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int6
 #define LS_WIN_CASE(R)                                                                                   \
             case R:                                                                                      \
                 hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, \
-                                   s0, rb0, A, lda, b, w.woff, w.nstep, w.lst, w.rloc, scale, B, ldb,     \
+                                   s0, rb0, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb,             \
                                    Sb, ldsb);                                                            \
                 break;
             LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
