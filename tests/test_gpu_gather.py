@@ -7,7 +7,9 @@ same order as the oracle's loop over j, so every case is bit-exact against the o
 the per-row gather (LS_OPT_GATHER = 1).  The shapes cover: m not a multiple of the 4096-row list
 window; d not a multiple of a work-group's rows; rows per group of 4, 12 and 20; more than one launch
 per slice group; S b alone in a last slice (n = 513), or starting a slice (n = 640); no right-hand
-side; padded lda and ldb; FP32 output; and subnormal inputs, whose sums stay subnormal."""
+side; padded lda and ldb; FP32 output; and subnormal inputs, whose sums stay subnormal.  The lists
+are built straight from the embedding when 512 zeta <= d <= 40960 and from the CSR otherwise; both
+builders are covered, including d on either side of 512 zeta."""
 import numpy as np
 import pytest
 
@@ -60,6 +62,19 @@ def test_window_gather_bit_exact(ctx, m, n, d):
     B1, Sb1 = sketch_mode(ctx, 1, dev(A)[:, :n], dev(b), d, 8, 31)
     assert np.array_equal(host(B1), eB)
     assert np.array_equal(host(Sb1), eSb)
+
+
+# d = 512 zeta is the smallest d whose lists are built from the embedding; d = 512 zeta - 1 takes the CSR.
+@pytest.mark.parametrize("zeta,d", [(8, 4096), (8, 4095), (4, 2048), (4, 2047), (16, 8192), (16, 8191)])
+def test_window_gather_list_builders(ctx, zeta, d):
+    m, n = 70001, 460
+    rng = np.random.default_rng(zeta * 100003 + d)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    B, Sb = ctx.sketch(dev(A), dev(b), d, zeta, 41)
+    eB, eSb = oracle.sketch(A, b, n, d, zeta, 41)
+    assert np.array_equal(host(B), eB)
+    assert np.array_equal(host(Sb), eSb)
 
 
 def test_window_gather_no_rhs_padded_ldb(ctx):
