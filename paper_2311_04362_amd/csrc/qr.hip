@@ -258,6 +258,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 // co-resident (cooperative launch), and each grid barrier spins a bounded number of times: if the
 // bound is ever reached the kernel flags ST_TIMEOUT and runs to completion, so it always exits.
 constexpr unsigned kSpinLimit = 1u << 20;
+constexpr int kBarFlags = 1024;             // step flags: at most this many work-groups per panel
 
 // Calls f(std::integral_constant<int, J>{}) for J = 0, 1, ... in order.
 template <class F, int... J>
@@ -268,8 +269,9 @@ __device__ __forceinline__ void for_each_column(F &f, std::integer_sequence<int,
 
 // Grid barrier by per-work-group step flags: after publishing its data, work-group g stores
 // flag[g] = epoch with release semantics; the barrier waits until every flag has reached epoch.
-// Flags only grow, so they need no reset within a launch.  The wait is bounded: past kSpinLimit
-// polls the kernel flags ST_TIMEOUT and continues, so every work-group always finishes.
+// Flags only grow (epochs rise over the panels of a factorization), so they need no reset between
+// panels.  The wait is bounded: past kSpinLimit polls the kernel flags ST_TIMEOUT and continues,
+// so every work-group always finishes.
 __device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned epoch, int32_t *status)
 {
     __syncthreads();
@@ -297,7 +299,7 @@ template <typename E, int RPT>
 __global__ void __launch_bounds__(kRB)
 k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t ldw,
              E *__restrict__ V, E *__restrict__ red, E *__restrict__ tau,
-             unsigned *__restrict__ bar, int32_t *__restrict__ status)
+             unsigned *__restrict__ bar, unsigned epoch0, int32_t *__restrict__ status)
 {
     __shared__ E s_tl[kNB];
     __shared__ E s_f[kNB];
@@ -366,7 +368,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             rb[(int64_t)blockIdx.x * kNB + tid] = acc;
             if (s_haspiv) piv[pb * kNB + tid] = s_piv[tid];
         }
-        flag_barrier(bar, nwg, (unsigned)(jc + 1), status);
+        flag_barrier(bar, nwg, epoch0 + (unsigned)(jc + 1), status);
         // (2) every work-group reduces the partials in the same fixed order
         {
             constexpr int NS = kRB / kNB;
@@ -760,7 +762,7 @@ static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb)
     qb.Z = ar.take<E>((size_t)kNB * (size_t)qb.ldw);
     qb.qtb = ar.take<E>((size_t)n);
     qb.RT = ar.take<E>((size_t)n * (size_t)n);
-    qb.bar = ar.take<unsigned>(1024);
+    qb.bar = ar.take<unsigned>(kBarFlags);
 }
 
 void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb) { qr_bufs_impl(ar, d, n, qb); }
@@ -827,12 +829,17 @@ int coop_capacity()
     return cache[dev];
 }
 
+// The step flags carry epochs that grow over all panels of one factorization (panel p uses
+// p (kNB + 1) + 1 ... p (kNB + 1) + kNB), so they are cleared once, before its first cooperative
+// panel (zero_flags), not before every panel.
 template <typename E, int RPT>
 hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, E *W,
-                             int64_t ldw, E *V, E *red, E *tau, unsigned *bar, int32_t *status)
+                             int64_t ldw, E *V, E *red, E *tau, unsigned *bar, bool zero_flags,
+                             int32_t *status)
 {
-    hipLaunchKernelGGL(k_zero_u32, dim3((nwg + 255) / 256), dim3(256), 0, s, bar, nwg);
-    void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &status};
+    if (zero_flags) hipLaunchKernelGGL(k_zero_u32, dim3(kBarFlags / 256), dim3(256), 0, s, bar, kBarFlags);
+    unsigned epoch0 = (unsigned)(p0 / kNB) * (unsigned)(kNB + 1);
+    void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &epoch0, &status};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT>), dim3(nwg),
                                       dim3(kRB), args, 0, s);
 }
@@ -841,7 +848,7 @@ hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int 
 // the per-column path.
 template <typename E>
 bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb,
-                       int32_t *status, hipError_t &err)
+                       bool &flags_zeroed, int32_t *status, hipError_t &err)
 {
     // One row per thread, as in k_panel_step: the work-groups' partial sums are then grouped exactly
     // as the per-column path groups them, so the two paths give the same bits.  A grid too large
@@ -849,8 +856,10 @@ bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBu
     const int64_t rows = d - p0;
     err = hipSuccess;
     const int nwg = (int)ceil_div(rows, kRB);
-    if (nwg <= coop_capacity<E, 1>()) {
-        err = launch_panel_coop<E, 1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar, status);
+    if (nwg <= coop_capacity<E, 1>() && nwg <= kBarFlags) {
+        err = launch_panel_coop<E, 1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar,
+                                      !flags_zeroed, status);
+        flags_zeroed = true;
         return true;
     }
     return false;
@@ -863,11 +872,12 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
     const int64_t ldw = qb.ldw;
     const int64_t red_stride = panel_wgs_max(d) * kNB + kNB;
     E *redA = qb.red, *redB = qb.red + red_stride;
+    bool flags_zeroed = false;
     for (int64_t p0 = 0; p0 < n; p0 += kNB) {
         const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
         const int64_t rows = d - p0;
         hipError_t err = hipSuccess;
-        if (per_column || !panel_cooperative(s, d, p0, nbp, qb, status, err)) {
+        if (per_column || !panel_cooperative(s, d, p0, nbp, qb, flags_zeroed, status, err)) {
             const int nwg = (int)ceil_div(rows, kRB);
             E *rin = redA, *rout = redB;
             for (int jc = -1; jc < nbp; ++jc) {
