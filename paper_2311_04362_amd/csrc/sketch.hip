@@ -12,8 +12,12 @@
 //                   row's columns in ascending j, times fl(1/sqrt(zeta)).  Rows of A are read as
 //                   coalesced 512-byte segments (non-temporal); no atomics on floating-point data.
 //                   Every row of A is fetched from HBM once per nonzero of its column of S (zeta x).
+//   k_wl_hist, k_wl_wscan, k_wl_place
+//                   the entry lists of k_gather_win straight from the embedding (no CSR), when
+//                   d <= kLdsRows and d >= 512 zeta: each group of sketch rows' entries, window by
+//                   window, rows in order, ascending j (below).
 //   k_win_count, k_win_scan, k_win_scatter
-//                   reorder each group of sketch rows' CSR entries window by window (below).
+//                   the same lists from the CSR, for the other shapes.
 //   k_gather_win    the same sums with each row of A fetched from HBM once or twice, not zeta times:
 //                   a work-group owns a 64-column slice of 16*rw sketch rows, accumulated in LDS;
 //                   the eight slices that share rows of A run on the eight XCDs at the same time
