@@ -24,7 +24,7 @@
 namespace {
 
 constexpr int kNB = 32;     // panel width
-constexpr int kRB = 256;    // rows per work-group in the panel kernels
+constexpr int kRB = 512;    // rows per work-group in the panel kernels (8 waves; 256 and 128 measured slower)
 
 // 16x16x4 MFMA per element type.  Operand layout (checked on gfx950 for both): A[i][kk] from lane
 // i + 16 kk, B[kk][j] from lane j + 16 kk.  The accumulator layouts differ: element q of a lane's
