@@ -2,7 +2,7 @@
 // fourth lines; eq. it-sk-qr; sketch-and-solve start eq. sketched_ls).
 //
 // Panels of kNB columns.  Inside a panel the reflectors are computed one column per launch
-// (k_panel_step): every work-group owns kRB consecutive rows held in registers; each launch
+// (k_panel_step): every work-group owns RB consecutive rows held in registers; each launch
 // (1) reduces, in a fixed order, the partial sums the previous launch left for this column,
 // (2) forms the reflector H = I - tau v v^T with beta = -sign(alpha) ||column||, sign(0) = +1,
 // (3) applies it to the rest of the panel, and (4) leaves the partial sums for the next column.
@@ -24,7 +24,14 @@
 namespace {
 
 constexpr int kNB = 32;     // panel width
-constexpr int kRB = 512;    // rows per work-group in the panel kernels (8 waves; 256 and 128 measured slower)
+// Rows per work-group in the panel kernels (one per thread), chosen from d alone so that both panel
+// paths factor a given matrix alike: 512 rows (8 waves) for d >= kRBLargeFrom, where it measured
+// fastest (205 -> 182 us per panel at d = 10^4), else 256, which keeps more work-groups per
+// one-column launch for the small sketches of the served stream.
+constexpr int kRBSmall = 256;
+constexpr int kRBLarge = 512;
+constexpr int64_t kRBLargeFrom = 8192;
+inline int panel_rows(int64_t d) { return d >= kRBLargeFrom ? kRBLarge : kRBSmall; }
 
 // 16x16x4 MFMA per element type.  Operand layout (checked on gfx950 for both): A[i][kk] from lane
 // i + 16 kk, B[kk][j] from lane j + 16 kk.  The accumulator layouts differ: element q of a lane's
@@ -137,8 +144,8 @@ __device__ __forceinline__ int transpose_sum_index(int lane)
 //   red_in[w * kNB + l] = sum over rows of w (rows >= k) of W[i,k] W[i,p0+l]
 //   piv_in[l]           = W[k, p0+l] (the pivot row, before this step)
 // The launch writes the same quantities for column k+1 into red_out/piv_out.
-template <typename E>
-__global__ void __launch_bounds__(kRB)
+template <typename E, int RB>
+__global__ void __launch_bounds__(RB)
 k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W, int64_t ldw,
              E *__restrict__ V, const E *__restrict__ red_in,
              const E *__restrict__ piv_in, E *__restrict__ red_out,
@@ -146,12 +153,12 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 {
     __shared__ E s_tl[kNB];
     __shared__ E s_f[kNB];
-    __shared__ E s_red[kRB / kNB][kNB];
-    __shared__ E s_part[kRB / 64][kNB];
+    __shared__ E s_red[RB / kNB][kNB];
+    __shared__ E s_part[RB / 64][kNB];
     __shared__ E s_scal[2];                       // beta, v_k
     const int tid = threadIdx.x;
     const int64_t k = p0 + jc;
-    const int64_t i = p0 + (int64_t)blockIdx.x * kRB + tid;   // this thread's row
+    const int64_t i = p0 + (int64_t)blockIdx.x * RB + tid;   // this thread's row
     const bool row_ok = i < d;
 
     E w[kNB];
@@ -160,7 +167,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 
     if (jc >= 0) {
         {   // reduce the partials: 8 contiguous groups of work-groups, then the groups in order
-            constexpr int NS = kRB / kNB;
+            constexpr int NS = RB / kNB;
             const int l = tid % kNB, sl = tid / kNB;
             const int per = (nwg + NS - 1) / NS;
             const int g0 = sl * per;
@@ -246,14 +253,14 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
         if (tid < kNB) {
             E acc = E(0);
 #pragma unroll
-            for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
+            for (int g = 0; g < RB / 64; ++g) acc += s_part[g][tid];
             red_out[blockIdx.x * kNB + tid] = acc;
         }
     }
 }
 
 // ---- Cooperative panel: one launch factors all kNB columns of a panel --------------------------
-// Each work-group keeps RPT * kRB rows of the panel in registers for the whole panel; a column step
+// Each work-group keeps RPT * RB rows of the panel in registers for the whole panel; a column step
 // is local arithmetic plus one grid-wide exchange of kNB partial sums.  All work-groups are
 // co-resident (cooperative launch), and each grid barrier spins a bounded number of times: if the
 // bound is ever reached the kernel flags ST_TIMEOUT and runs to completion, so it always exits.
@@ -295,23 +302,23 @@ __device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned 
     __syncthreads();
 }
 
-template <typename E, int RPT>
-__global__ void __launch_bounds__(kRB)
+template <typename E, int RPT, int RB>
+__global__ void __launch_bounds__(RB)
 k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t ldw,
              E *__restrict__ V, E *__restrict__ red, E *__restrict__ tau,
              unsigned *__restrict__ bar, unsigned epoch0, int32_t *__restrict__ status)
 {
     __shared__ E s_tl[kNB];
     __shared__ E s_f[kNB];
-    __shared__ E s_part[kRB / 64][kNB];
-    __shared__ E s_red[kRB / kNB][kNB];
+    __shared__ E s_part[RB / 64][kNB];
+    __shared__ E s_red[RB / kNB][kNB];
     __shared__ E s_scal[2];
     __shared__ E s_piv[kNB];
     __shared__ int s_haspiv;
     // The panel's Householder vectors for this work-group's rows, column-major (conflict-free):
     // written to V once after the last column, so the barriers' release fences do not also push
     // V stores out of L2 at every column.
-    __shared__ E s_v[kNB][RPT * kRB];
+    __shared__ E s_v[kNB][RPT * RB];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     E *piv = red + 2 * (int64_t)nwg * kNB;            // 2 x kNB pivot rows
     const int tidx = transpose_sum_index(lane);
@@ -320,7 +327,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
     E w[RPT][kNB];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * kRB + tid;
+        row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * RB + tid;
         ok[r] = row[r] < d;
 #pragma unroll
         for (int l = 0; l < kNB; ++l) w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : E(0);
@@ -364,14 +371,14 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
         if (tid < kNB) {
             E acc = E(0);
 #pragma unroll
-            for (int g = 0; g < kRB / 64; ++g) acc += s_part[g][tid];
+            for (int g = 0; g < RB / 64; ++g) acc += s_part[g][tid];
             rb[(int64_t)blockIdx.x * kNB + tid] = acc;
             if (s_haspiv) piv[pb * kNB + tid] = s_piv[tid];
         }
         flag_barrier(bar, nwg, epoch0 + (unsigned)(jc + 1), status);
         // (2) every work-group reduces the partials in the same fixed order
         {
-            constexpr int NS = kRB / kNB;
+            constexpr int NS = RB / kNB;
             const int l = tid % kNB, sl = tid / kNB;
             const int per = (nwg + NS - 1) / NS;
             const int g0 = sl * per;
@@ -418,7 +425,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             if (!ok[r]) continue;
             const bool below = row[r] >= k;
             const E vi = (row[r] == k) ? s_scal[1] : w[r][jc];
-            s_v[jc][r * kRB + tid] = below ? vi : E(0);
+            s_v[jc][r * RB + tid] = below ? vi : E(0);
             if (!below) continue;
 #pragma unroll
             for (int l = jc + 1; l < kNB; ++l)
@@ -435,7 +442,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
         E *vrow = V + (row[r] - p0) * kNB;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) vrow[l] = (l < nbp) ? s_v[l][r * kRB + tid] : E(0);
+        for (int l = 0; l < kNB; ++l) vrow[l] = (l < nbp) ? s_v[l][r * RB + tid] : E(0);
     }
 }
 
@@ -736,7 +743,7 @@ k_rank_check(int64_t n, const E *__restrict__ RT, int32_t *__restrict__ status)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int64_t panel_wgs_max(int64_t d) { return ceil_div(d, kRB); }
+int64_t panel_wgs_max(int64_t d) { return ceil_div(d, kRBSmall); }
 
 int64_t chunk_rows(int64_t rows)
 {
@@ -809,7 +816,7 @@ namespace {
 
 // Work-groups of k_panel_coop<E, RPT> that can be co-resident on the current device (0: cooperative
 // launch unavailable).  Cached per device.
-template <typename E, int RPT>
+template <typename E, int RPT, int RB>
 int coop_capacity()
 {
     static int cache[64];
@@ -819,7 +826,7 @@ int coop_capacity()
     int coop = 0, cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<E, RPT>), kRB, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB>), RB, 0) != hipSuccess ||
         per_cu <= 0) {
         (void)hipGetLastError();
         cache[dev] = -1;
@@ -832,7 +839,7 @@ int coop_capacity()
 // The step flags carry epochs that grow over all panels of one factorization (panel p uses
 // p (kNB + 1) + 1 ... p (kNB + 1) + kNB), so they are cleared once, before its first cooperative
 // panel (zero_flags), not before every panel.
-template <typename E, int RPT>
+template <typename E, int RPT, int RB>
 hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, E *W,
                              int64_t ldw, E *V, E *red, E *tau, unsigned *bar, bool zero_flags,
                              int32_t *status)
@@ -840,13 +847,13 @@ hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int 
     if (zero_flags) hipLaunchKernelGGL(k_zero_u32, dim3(kBarFlags / 256), dim3(256), 0, s, bar, kBarFlags);
     unsigned epoch0 = (unsigned)(p0 / kNB) * (unsigned)(kNB + 1);
     void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &epoch0, &status};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT>), dim3(nwg),
-                                      dim3(kRB), args, 0, s);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB>), dim3(nwg),
+                                      dim3(RB), args, 0, s);
 }
 
 // One panel by the cooperative kernel if the device can hold its grid; returns false to request
 // the per-column path.
-template <typename E>
+template <typename E, int RB>
 bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb,
                        bool &flags_zeroed, int32_t *status, hipError_t &err)
 {
@@ -855,9 +862,9 @@ bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBu
     // to be co-resident takes the per-column path.
     const int64_t rows = d - p0;
     err = hipSuccess;
-    const int nwg = (int)ceil_div(rows, kRB);
-    if (nwg <= coop_capacity<E, 1>() && nwg <= kBarFlags) {
-        err = launch_panel_coop<E, 1>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar,
+    const int nwg = (int)ceil_div(rows, RB);
+    if (nwg <= coop_capacity<E, 1, RB>() && nwg <= kBarFlags) {
+        err = launch_panel_coop<E, 1, RB>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar,
                                       !flags_zeroed, status);
         flags_zeroed = true;
         return true;
@@ -877,13 +884,22 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
         const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
         const int64_t rows = d - p0;
         hipError_t err = hipSuccess;
-        if (per_column || !panel_cooperative(s, d, p0, nbp, qb, flags_zeroed, status, err)) {
-            const int nwg = (int)ceil_div(rows, kRB);
+        const int rb = panel_rows(d);
+        const bool coop = !per_column && (rb == kRBLarge
+                                              ? panel_cooperative<E, kRBLarge>(s, d, p0, nbp, qb, flags_zeroed, status, err)
+                                              : panel_cooperative<E, kRBSmall>(s, d, p0, nbp, qb, flags_zeroed, status, err));
+        if (!coop) {
+            const int nwg = (int)ceil_div(rows, rb);
             E *rin = redA, *rout = redB;
             for (int jc = -1; jc < nbp; ++jc) {
-                hipLaunchKernelGGL(k_panel_step<E>, dim3(nwg), dim3(kRB), 0, s, d, p0, nbp, jc, nwg, qb.W,
-                                   ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
-                                   rout + (int64_t)nwg * kNB, qb.tau, status);
+                if (rb == kRBLarge)
+                    hipLaunchKernelGGL((k_panel_step<E, kRBLarge>), dim3(nwg), dim3(kRBLarge), 0, s, d, p0, nbp, jc,
+                                       nwg, qb.W, ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                                       rout + (int64_t)nwg * kNB, qb.tau, status);
+                else
+                    hipLaunchKernelGGL((k_panel_step<E, kRBSmall>), dim3(nwg), dim3(kRBSmall), 0, s, d, p0, nbp, jc,
+                                       nwg, qb.W, ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                                       rout + (int64_t)nwg * kNB, qb.tau, status);
                 E *t = rin;
                 rin = rout;
                 rout = t;

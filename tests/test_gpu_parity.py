@@ -144,10 +144,12 @@ def test_qr_sketch_vs_oracle(ctx, d, n, kappa, panel):
         ctx.set_option(ls.OPT_QR_PANEL, 0)
 
 
-def test_qr_panel_paths_agree_bitwise(ctx):
+# d = 8192 is the first d whose panels take 512-row work-groups (256 below).
+@pytest.mark.parametrize("d", [3000, 8191, 8192, 12001])
+def test_qr_panel_paths_agree_bitwise(ctx, d):
     """Both panel implementations do the same arithmetic in the same order."""
-    rng = np.random.default_rng(3)
-    B, Sb = dev(rng.standard_normal((3000, 70))), dev(rng.standard_normal(3000))
+    rng = np.random.default_rng(3 + d)
+    B, Sb = dev(rng.standard_normal((d, 70))), dev(rng.standard_normal(d))
     R0, x0 = ctx.qr_sketch(B, Sb)
     ctx.set_option(ls.OPT_QR_PANEL, 1)
     R1, x1 = ctx.qr_sketch(B, Sb)
