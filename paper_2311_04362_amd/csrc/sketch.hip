@@ -588,6 +588,117 @@ k_wl_place(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
     }
 }
 
+// k_wl_place with the window staged in LDS (zeta <= 8, d <= kStageRows): the window's entries are
+// placed at window-local positions (16-bit row counters, two to an LDS word), each (window, row)
+// segment is sorted there by j, and each group's segment then goes to its list with contiguous
+// stores.  Same lists as k_wl_place.
+constexpr int kStageEntries = (int)kWinLen * 8;          // a window's entries for zeta <= 8 (128 KiB)
+constexpr int64_t kStageRows = 15360;                    // 16-bit counters in the remaining LDS
+
+template <int RW>
+__global__ void __launch_bounds__(1024)
+k_wl_place_lds(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
+               const uint32_t *__restrict__ ent, const int32_t *__restrict__ cnt,
+               const int32_t *__restrict__ rel, const int32_t *__restrict__ gstart,
+               const int32_t *__restrict__ gtot, int32_t *__restrict__ woff, uint32_t *__restrict__ lst)
+{
+    __shared__ uint32_t loc[kStageEntries];
+    __shared__ uint32_t h2[kStageRows / 2];              // row k's counter: half (k & 1) of word k / 2
+    const int64_t w = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t ngroups = (d + RW - 1) / RW;
+    const int32_t *c = cnt + w * d;
+    for (int64_t q = tid; q < (d + 1) / 2; q += blockDim.x) h2[q] = 0u;
+    for (int64_t g = tid; g < ngroups; g += blockDim.x) {
+        if (w % kWinPerStep == 0) woff[g * (nstep + 1) + w / kWinPerStep] = gstart[g] + rel[g * nwl + w];
+        if (w == nwl - 1) woff[g * (nstep + 1) + nstep] = gstart[g] + gtot[g];
+    }
+    // Window-local start of each row: exclusive scan of the row counts in row order (rows of a
+    // group are consecutive, so each group's entries form one local segment).  Thread t takes
+    // rows [t per, (t+1) per); the 1024 partial sums are scanned in loc[] before it holds entries.
+    int32_t *part = reinterpret_cast<int32_t *>(loc);
+    const int64_t per = (d + 1023) / 1024;
+    const int64_t r0 = tid * per, r1 = (r0 + per < d) ? r0 + per : d;
+    int32_t sum = 0;
+    for (int64_t k = r0; k < r1; ++k) sum += c[k];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = (tid >= off) ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - sum;
+    __syncthreads();                                     // part[] is read; loc[] is free again
+    for (int64_t k = r0; k < r1; ++k) {                  // two threads may share a word: atomics
+        atomicAdd(&h2[k >> 1], (uint32_t)run << (16 * (k & 1)));
+        run += c[k];
+    }
+    __syncthreads();
+    const int64_t j1 = ((w + 1) * kWinLen < m) ? (w + 1) * kWinLen : m;
+    for (int64_t i = w * kWinLen * zeta + tid; i < j1 * zeta; i += blockDim.x) {
+        const uint32_t v = ent[i];
+        const uint32_t k = v & 0x7FFFFFFFu;
+        const uint32_t sh = 16u * (k & 1u);
+        const uint32_t p = (atomicAdd(&h2[k >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        loc[p] = (uint32_t)(i / zeta) | ((k % RW) << kListJBits) | (v & 0x80000000u);
+    }
+    __syncthreads();
+    // sort each (window, row) segment by j in LDS
+    for (int64_t k = tid; k < d; k += blockDim.x) {
+        const int32_t hi = (int32_t)((h2[k >> 1] >> (16 * (k & 1))) & 0xFFFFu), lo = hi - c[k];
+        if (hi - lo <= 1) continue;
+        if (hi - lo <= 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) x[i] = (lo + i < hi) ? loc[lo + i] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int kk = 2; kk <= 16; kk <<= 1)
+#pragma unroll
+                for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int l = i ^ jj;
+                        if (l <= i) continue;
+                        const bool up = (i & kk) == 0;
+                        const uint32_t a = x[i], b = x[l];
+                        const bool swap = up ? ((a & kListJMask) > (b & kListJMask))
+                                             : ((a & kListJMask) < (b & kListJMask));
+                        x[i] = swap ? b : a;
+                        x[l] = swap ? a : b;
+                    }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (lo + i < hi) loc[lo + i] = x[i];
+            continue;
+        }
+        for (int32_t i = lo + 1; i < hi; ++i) {
+            const uint32_t x = loc[i];
+            int32_t q = i - 1;
+            while (q >= lo && (loc[q] & kListJMask) > (x & kListJMask)) {
+                loc[q + 1] = loc[q];
+                --q;
+            }
+            loc[q + 1] = x;
+        }
+    }
+    __syncthreads();
+    // each group's segment to its list, one wave per group, 64 consecutive entries per store
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int64_t g = wave; g < ngroups; g += blockDim.x / 64) {
+        const int64_t kl = g * RW + RW - 1 < d ? g * RW + RW - 1 : d - 1;   // last row of the group
+        const int32_t end = (int32_t)((h2[kl >> 1] >> (16 * (kl & 1))) & 0xFFFFu);
+        int32_t beg = 0;
+        if (g > 0) {
+            const int64_t kp = g * RW - 1;                                  // last row of group g-1
+            beg = (int32_t)((h2[kp >> 1] >> (16 * (kp & 1))) & 0xFFFFu);
+        }
+        uint32_t *dst = lst + gstart[g] + rel[g * nwl + w];
+        for (int32_t e = beg + lane; e < end; e += 64) dst[e - beg] = loc[e];
+    }
+}
+
 // Work-group (XCD x = blockIdx % 8, block blockIdx / 8) takes column slice slice0 + x and row block
 // rb0 + blockIdx / 8 (16 groups of RW sketch rows, one per wave).  Lane l of a wave owns column
 // 64*slice + l of its RW rows in LDS; column n is S b (lane reads b).  The wave walks its group's
@@ -763,8 +874,12 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
             hipLaunchKernelGGL(k_wl_wscan, dim3(blocks_for(ngroups, 4)), dim3(256), 0, s, ngroups, w.nwl,  \
                                w.rel, w.gtot);                                                            \
             hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, ngroups, w.gtot, w.gstart, sb.fill); \
-            hipLaunchKernelGGL(k_wl_place<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta, w.nwl,  \
-                               w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst);           \
+            if (zeta <= 8 && d <= kStageRows)                                                             \
+                hipLaunchKernelGGL(k_wl_place_lds<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta,  \
+                                   w.nwl, w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst); \
+            else                                                                                          \
+                hipLaunchKernelGGL(k_wl_place<R>, dim3((unsigned)w.nwl), dim3(1024), 0, s, m, d, zeta,      \
+                                   w.nwl, w.nstep, sb.ent, w.cnt, w.rel, w.gstart, w.gtot, w.woff, w.lst); \
             break;
         LS_WL_CASE(4) LS_WL_CASE(8) LS_WL_CASE(12) LS_WL_CASE(16) LS_WL_CASE(20)
 #undef LS_WL_CASE
