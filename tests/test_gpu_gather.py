@@ -48,10 +48,11 @@ def sketch_mode(ctx, mode, *args, **kw):
 
 # (m, n, d): rows per group 4 (d = 1000), 20 (d = 10007), 12 with two launches (d = 12000), 20 with
 # four launches (d = 40960, 40961).  d = 40960 is the largest d whose lists are built straight from
-# the embedding (its row counters fill the 160 KiB of LDS); 40961 takes the CSR.
+# the embedding (its row counters fill the 160 KiB of LDS); 40961 takes the CSR.  d = 15360 is the
+# largest d whose window is placed in LDS; 15361 places it in the list directly.
 @pytest.mark.parametrize("m,n,d", [(70001, 448, 1000), (70001, 500, 10007), (65536, 513, 3000),
-                                   (70001, 640, 2001), (66000, 1000, 12000), (70001, 448, 40960),
-                                   (70001, 448, 40961)])
+                                   (70001, 640, 2001), (66000, 1000, 12000), (70001, 448, 15360),
+                                   (70001, 448, 15361), (70001, 448, 40960), (70001, 448, 40961)])
 def test_window_gather_bit_exact(ctx, m, n, d):
     rng = np.random.default_rng(m + 3 * n + d)
     lda = n + 5
