@@ -74,7 +74,7 @@ enum {
     LS_OPT_GAMMA = 10,      /* gamma of that rule (dval, default 1)                              */
     LS_OPT_RHO = 11,        /* rho of that rule (dval, default 0.04)                             */
     LS_OPT_GATHER = 12      /* 0: the column-sliced sketch gather when the shape suits it (n >= 448,
-                               m >= 65536); 1: one wave per sketch row always.  Same bits.      */
+                               65536 <= m < 2^26); 1: one wave per sketch row always.  Same bits. */
 };
 ls_status ls_set_option(ls_ctx *ctx, int key, int64_t ival, double dval);
 ls_status ls_get_option(const ls_ctx *ctx, int key, int64_t *ival, double *dval);
