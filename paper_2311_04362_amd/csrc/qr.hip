@@ -26,9 +26,9 @@ namespace {
 constexpr int kNB = 32;     // panel width
 // Rows per work-group in the panel kernels (one per thread), chosen from d alone so that both panel
 // paths factor a given matrix alike: 512 rows (8 waves) for d >= kRBLargeFrom, where it measured
-// fastest (205 -> 182 us per panel at d = 10^4), else 256, which keeps more work-groups per
-// one-column launch for the small sketches of the served stream.
-constexpr int kRBSmall = 256;
+// fastest (205 -> 182 us per panel at d = 10^4), else 128 (2 waves), which gives the one-column
+// launches of the served stream's small sketches more work-groups (687 -> 750 solves/s against 256).
+constexpr int kRBSmall = 128;
 constexpr int kRBLarge = 512;
 constexpr int64_t kRBLargeFrom = 8192;
 inline int panel_rows(int64_t d) { return d >= kRBLargeFrom ? kRBLarge : kRBSmall; }
