@@ -19,6 +19,8 @@
  *   orc_sketch              B = S A and S b, Algorithm 2 (second line)
  *   orc_householder_lstsq   Householder-QR least squares, Section 2.1 (backward-stable reference,
  *                           eq. ls_backward); also the sketch-and-solve start, eq. (sketched_ls)
+ *   orc_tsqr_lstsq          the same method in TSQR form (a reduction tree of Householder
+ *                           factorizations over row blocks, on host threads) for large m
  *   orc_residual_gradient   r_i = b - A x_i and c_i = A^T r_i, Algorithm 2 loop body
  *   orc_solve_rt/orc_solve_r the two triangular solves of Algorithm 2, Section 3.2
  *   orc_iterative_sketching Algorithm 2 end to end
@@ -212,6 +214,124 @@ int orc_householder_lstsq(int64_t rows, int64_t n, const double *M, int64_t ldm,
                 for (int64_t c = 0; c < n; ++c) R[i * ldr + c] = Rl[i * n + c];
     }
     free(W); free(v); free(wt); free(Rl);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Householder least squares in TSQR form ("tall-skinny QR": Demmel, Grigori, Hoemmen & Langou,
+ * SIAM J. Sci. Comput. 34, 2012), the same backward-stable method as orc_householder_lstsq
+ * (Section 2.1) organised as a reduction tree so that it reaches m in the millions on host cores.
+ *
+ * The augmented matrix [A | b] (m x (n+1)) is cut into row blocks of block_rows rows (the last block
+ * takes the remainder, so it has block_rows .. 2 block_rows - 1 rows).  Each block is factored by
+ * orc_householder_lstsq, which yields its triangular factor R_i, (Q_i^T b_i)[0:n] and the norm
+ * rho_i of the rest of Q_i^T b_i: together the (n+1) x (n+1) upper-triangular factor
+ *     T_i = [[R_i, (Q_i^T b_i)[0:n]], [0, rho_i]]
+ * of [A_i | b_i] (T_i^T T_i = [A_i | b_i]^T [A_i | b_i]).  The T_i are stacked in groups of
+ * f = max(2, floor(block_rows / (n+1))) and each stacked group is factored the same way (a group of
+ * one is passed on unchanged), level after level, until one T remains.  Its leading n x n block is
+ * the R of [A | b] up to row signs, and x solves R x = T[0:n, n] by back substitution;
+ * |T[n, n]| = ||b - A x|| is a by-product (the last reflection's norm).
+ *
+ * Blocks of one level are independent and run on up to nthreads host threads (OpenMP); the tree
+ * does not depend on the thread count, so neither do the bits of the result.
+ * Every block must have full column rank (true with probability one for data drawn from a
+ * continuous distribution); returns 0, 1 on bad arguments (block_rows < n + 1, m < n), 2 on
+ * allocation failure, 3 + k when the final R has R[k,k] == 0, 4 + n when a block is rank deficient.
+ * R (nullable, n x n, ldr) receives the final R, resid (nullable) |T[n, n]|. */
+int orc_tsqr_lstsq(int64_t m, int64_t n, const double *A, int64_t lda, const double *b,
+                   int64_t block_rows, int32_t nthreads, double *x, double *R, int64_t ldr,
+                   double *resid)
+{
+    if (n < 1 || m < n || lda < n || block_rows < n + 1 || (R && ldr < n) || nthreads < 1) return 1;
+    const int64_t w = n + 1;
+    int64_t nblk = m / block_rows;
+    if (nblk < 1) nblk = 1;
+    double *T = (double *)malloc(sizeof(double) * (size_t)nblk * (size_t)w * (size_t)w);
+    int *brc = (int *)malloc(sizeof(int) * (size_t)nblk);
+    if (!T || !brc) { free(T); free(brc); return 2; }
+
+    /* level 0: row blocks of [A | b] */
+    #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int64_t i = 0; i < nblk; ++i) {
+        const int64_t r0 = i * block_rows;
+        const int64_t r1 = (i == nblk - 1) ? m : r0 + block_rows;
+        double *Ti = T + (size_t)i * (size_t)w * (size_t)w;
+        double *qtb = (double *)malloc(sizeof(double) * (size_t)n);
+        double rho = 0.0;
+        int rc = qtb ? orc_householder_lstsq(r1 - r0, n, A + r0 * lda, lda, b + r0, Ti, w, qtb, NULL, &rho) : 2;
+        if (rc == 0) {
+            for (int64_t k = 0; k < n; ++k) Ti[k * w + n] = qtb[k];
+            for (int64_t c = 0; c < w; ++c) Ti[n * w + c] = 0.0;
+            Ti[n * w + n] = rho;
+        }
+        brc[i] = rc;
+        free(qtb);
+    }
+    int rc = 0;
+    for (int64_t i = 0; i < nblk; ++i)
+        if (brc[i]) rc = (brc[i] == 2) ? 2 : 4 + (int)n;
+    /* upper levels: groups of f stacked factors */
+    const int64_t f = (block_rows / w) > 2 ? block_rows / w : 2;
+    int64_t cnt = nblk;
+    while (rc == 0 && cnt > 1) {
+        const int64_t ng = (cnt + f - 1) / f;
+        double *Tn = (double *)malloc(sizeof(double) * (size_t)ng * (size_t)w * (size_t)w);
+        if (!Tn) { rc = 2; break; }
+        #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+        for (int64_t g = 0; g < ng; ++g) {
+            const int64_t k0 = g * f;
+            const int64_t k1 = (k0 + f < cnt) ? k0 + f : cnt;
+            const double *Y = T + (size_t)k0 * (size_t)w * (size_t)w;   /* (k1-k0) w x w, ld w */
+            double *Tg = Tn + (size_t)g * (size_t)w * (size_t)w;
+            int grc = 0;
+            if (k1 - k0 == 1) {
+                memcpy(Tg, Y, sizeof(double) * (size_t)w * (size_t)w);
+            } else {
+                const int64_t rows = (k1 - k0) * w;
+                double *rhs = (double *)malloc(sizeof(double) * (size_t)rows);
+                double *qtb = (double *)malloc(sizeof(double) * (size_t)n);
+                double rho = 0.0;
+                if (!rhs || !qtb) grc = 2;
+                if (!grc) {
+                    for (int64_t r = 0; r < rows; ++r) rhs[r] = Y[r * w + n];
+                    grc = orc_householder_lstsq(rows, n, Y, w, rhs, Tg, w, qtb, NULL, &rho);
+                }
+                if (!grc) {
+                    for (int64_t k = 0; k < n; ++k) Tg[k * w + n] = qtb[k];
+                    for (int64_t c = 0; c < w; ++c) Tg[n * w + c] = 0.0;
+                    Tg[n * w + n] = rho;
+                }
+                free(rhs);
+                free(qtb);
+            }
+            brc[g] = grc;
+        }
+        for (int64_t g = 0; g < ng; ++g)
+            if (brc[g]) rc = (brc[g] == 2) ? 2 : 4 + (int)n;
+        free(T);
+        T = Tn;
+        cnt = ng;
+    }
+    if (rc == 0) {
+        for (int64_t k = 0; k < n; ++k)
+            if (T[k * w + k] == 0.0) { rc = 3 + (int)k; break; }
+    }
+    if (rc == 0) {
+        double *y = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!y) rc = 2;
+        else {
+            for (int64_t k = 0; k < n; ++k) y[k] = T[k * w + n];
+            if (x) orc_solve_r(n, T, w, y, x);
+            if (resid) *resid = fabs(T[n * w + n]);
+            if (R)
+                for (int64_t i = 0; i < n; ++i)
+                    for (int64_t c = 0; c < n; ++c) R[i * ldr + c] = (c >= i) ? T[i * w + c] : 0.0;
+            free(y);
+        }
+    }
+    free(T);
+    free(brc);
     return rc;
 }
 
