@@ -102,6 +102,18 @@ def cpu_baseline(w: dict, sample_rows: int):
                        f"-> {t_solve:.1f} s/solve")}
 
 
+def release_device():
+    """Wait for the device and return torch's cached blocks to HIP, so that no device memory,
+    event or stream work is still held when the interpreter (and a profiler's exit hooks) tear
+    down the runtime."""
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def timed_solves(ctx, A, b, d, q, x, reps):
     """Seconds per ls_solve (mean of reps after one warm-up) and the solve info of the last."""
     import torch
@@ -170,8 +182,9 @@ def bench_mixed(args, w):
         "speedup_q40_geomean": math.exp(sum(math.log(v) for v in speedups_q) / len(speedups_q)),
         "cases": cases,
     }
-    print(json.dumps(rec))
     ctx.close()
+    release_device()
+    print(json.dumps(rec), flush=True)
 
 
 def bench_large(args, w):
@@ -217,8 +230,10 @@ def bench_large(args, w):
         "mixed": out["mixed"], "fp64": out["fp64"],
         "mixed_speedup": out["fp64"]["ms"] / out["mixed"]["ms"],
     }
-    print(json.dumps(rec))
+    del p, A, b, x
     ctx.close()
+    release_device()
+    print(json.dumps(rec), flush=True)
 
 
 def served_problems(w, seed=7):
@@ -345,7 +360,9 @@ def bench_served(args, w):
         "forward_error_max": max(fe),
         **out,
     }
-    print(json.dumps(rec))
+    del probs, xs_sat, xs_base
+    release_device()
+    print(json.dumps(rec), flush=True)
 
 
 def main():
@@ -450,11 +467,15 @@ def main():
                                    "bytes_written_per_copy": src.numel() * 8,
                                    "ms_per_copy": ms, "GB/s": moved / (ms * 1e-3) / 1e9}
         del src, dst
+    # Release the problem, the context's workspace, events and pinned word before the CPU work and
+    # well before interpreter shutdown: nothing of HIP's is left for exit-time destructors.
+    del A, b, x, p
+    ctx.close()
+    release_device()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_rows)
-    print(json.dumps(rec))
-    ctx.close()
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":
