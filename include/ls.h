@@ -127,6 +127,20 @@ ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const do
 ls_status ls_gradient(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A, int64_t lda,
                       const double *b, const double *x, double *c, double *rnorm2);
 
+/* ---- ls_gradient without allocation ---------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, kernels and bits as ls_gradient, but the
+ * per-work-group partials of c and ||r||^2 live in a fixed 33 MiB scratch array that the library
+ * holds on each GPU it runs on until the process ends (its address is looked up once per device by
+ * ls_create), not in the context's workspace.  Nothing is allocated or freed (no hipMalloc, no
+ * events: LS_OPT_PROFILE does not time this call).  Every call on one GPU, from any context and any
+ * stream, uses that GPU's one array: calls that overlap on one GPU race and must be ordered by the
+ * caller; a call's results are complete once its stream has reached them.  The array needs no
+ * clearing (every partial is written before it is read).  LS_ERR_UNSUPPORTED if the partials
+ * exceed the array (not reachable for n <= LS_MAX_N); other errors as ls_gradient. */
+ls_status ls_gradient_noalloc(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A,
+                              int64_t lda, const double *b, const double *x, double *c, double *rnorm2);
+
 /* ---- The two triangular solves of Alg. 2: d = R^{-1} (R^{-T} c) by forward then back
  * substitution (never an explicit inverse).  R: n x n upper triangular, ldr >= n. */
 ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R, int64_t ldr,

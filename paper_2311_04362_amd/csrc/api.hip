@@ -425,6 +425,12 @@ ls_status ls_create(int device, ls_ctx **out)
         delete ctx;
         return LS_ERR_DEVICE;
     }
+    if (pass_scratch_attach(ctx) != LS_OK) {
+        (void)hipFree(ctx->status);
+        (void)hipHostFree(ctx->status_host);
+        delete ctx;
+        return LS_ERR_DEVICE;
+    }
     *out = ctx;
     return LS_OK;
 }
@@ -623,6 +629,36 @@ ls_status ls_gradient(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const dou
     IterBufs ib{};
     LS_TRY(with_arena(ctx, [&](Arena &ar) { iter_bufs(ar, m, n, ib, false); }));
     LS_TRY(timed_gradient(ctx, s, m, n, A, lda, b, x, ib, c, rnorm2));
+    return LS_OK;
+}
+
+ls_status ls_gradient_noalloc(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double *A,
+                              int64_t lda, const double *b, const double *x, double *c, double *rnorm2)
+{
+    if (!ctx) return LS_ERR_ARG;
+    LS_TRY(check_n(ctx, n));
+    if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
+    LS_TRY(check_mat(ctx, A, lda, n, "A"));
+    LS_TRY(check_vec(ctx, b, "b"));
+    LS_TRY(check_vec(ctx, x, "x"));
+    LS_TRY(check_vec(ctx, c, "c"));
+    LS_TRY(check_vec(ctx, rnorm2, "rnorm2", true));
+    LS_TRY(need_device(ctx));
+    if (!ctx->scratch) return ls_fail(ctx, LS_ERR_DEVICE, "no scratch address for this device");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // The same carve as ls_gradient (same P, hence the same kernels and bits), over the fixed array.
+    IterBufs ib{};
+    Arena sizing;
+    iter_bufs(sizing, m, n, ib, false);
+    if (sizing.off > kNoAllocScratchBytes)
+        return ls_fail(ctx, LS_ERR_UNSUPPORTED, "pass partials of " + std::to_string(sizing.off) +
+                                                    " bytes exceed the " + std::to_string(kNoAllocScratchBytes) +
+                                                    "-byte scratch");
+    Arena real;
+    real.base = static_cast<char *>(ctx->scratch);
+    iter_bufs(real, m, n, ib, false);
+    HIP_TRY(ctx, launch_gradient(s, m, n, A, lda, b, x, ib, c, rnorm2), "pass kernels");
     return LS_OK;
 }
 

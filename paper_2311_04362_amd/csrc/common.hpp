@@ -40,6 +40,7 @@ struct ls_ctx {
     size_t ws_bytes = 0;
     int32_t *status = nullptr;      // device status word
     int32_t *status_host = nullptr; // pinned host copy
+    void *scratch = nullptr;        // this device's copy of the fixed scratch (ls_gradient_noalloc)
     std::string err;
 };
 
@@ -196,6 +197,12 @@ struct IterBufs {
     int32_t P;
 };
 int32_t iter_partials(int64_t m, int64_t n);
+// Size of the fixed per-device scratch array of ls_gradient_noalloc (33 MiB: the partials of the
+// widest pass, 2048 x 2048 doubles, and the small vectors of an IterBufs carve).
+constexpr size_t kNoAllocScratchBytes = (size_t)33 << 20;
+// Looks up this device's address of that array (once per device; the device must be current) and
+// stores it in ctx->scratch.
+ls_status pass_scratch_attach(ls_ctx *ctx);
 
 // ---- served rounds (pass.hip, solve.hip; driven by server.hip) ----------------------------------
 // One resident problem of a served round.  Its pass runs as virtual work-groups 0..P-1 (P =

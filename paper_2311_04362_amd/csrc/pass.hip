@@ -5,6 +5,8 @@
 //              work-group writes one partial of c and of ||r||^2.  A is read exactly once, as
 //              coalesced segments of its rows; the grid is one wave of co-resident work-groups.
 //   k_reduce   sums the partials in a fixed order (deterministic c and ||r||^2).
+#include <mutex>
+
 #include "common.hpp"
 
 namespace {
@@ -306,6 +308,35 @@ hipError_t launch_served_reduce(hipStream_t s, int total_wg, const ServeSlot *sl
     if (total_wg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_served, dim3(total_wg), dim3(64 * kRedGroups), 0, s, slots, wg_slot);
     return hipGetLastError();
+}
+
+// Scratch of ls_gradient_noalloc: the P x n partials of c and the P partials of ||r||^2 (with the
+// rest of an IterBufs carve) for any n <= LS_MAX_N, P <= kMaxPartials.  One copy per GPU, held until
+// the process ends.  Host code never uses this name as an address: its device address on each GPU
+// comes from hipGetSymbolAddress (pass_scratch_attach).
+static_assert(kNoAllocScratchBytes >= (size_t)kMaxPartials * LS_MAX_N * sizeof(double) + (64u << 10),
+              "scratch must hold the partials of the widest pass");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+ls_status pass_scratch_attach(ls_ctx *ctx)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return ls_fail(ctx, LS_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[ctx->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return ls_fail(ctx, LS_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        }
+        addr[ctx->device] = p;
+    }
+    ctx->scratch = addr[ctx->device];
+    return LS_OK;
 }
 
 int32_t iter_partials(int64_t m, int64_t n)

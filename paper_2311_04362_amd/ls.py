@@ -28,7 +28,8 @@ EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_opti
            "ls_gradient", "ls_precond_solve", "ls_iterate", "ls_solve", "ls_sync", "ls_profile",
            "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32",
            "ls_server_create", "ls_server_destroy", "ls_server_submit", "ls_server_wait",
-           "ls_server_request_info", "ls_server_stats", "ls_server_last_error"]
+           "ls_server_request_info", "ls_server_stats", "ls_server_last_error",
+           "ls_gradient_noalloc"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -65,6 +66,7 @@ def load():
         "ls_sketch": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _u64, _vp, _i64, _vp], ctypes.c_int),
         "ls_qr_sketch": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp], ctypes.c_int),
         "ls_gradient": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "ls_gradient_noalloc": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
         "ls_precond_solve": ([_vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
         "ls_iterate": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp], ctypes.c_int),
         "ls_solve": ([_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _i32, _vp], ctypes.c_int),
@@ -192,6 +194,20 @@ class Context:
         rr = torch.empty(1, dtype=torch.float64, device=A.device)
         self._check(self._L.ls_gradient(self.h, self._stream(), m, n, _ptr(A), lda, _ptr(_vec(b, "b")),
                                         _ptr(_vec(x, "x")), _ptr(c), _ptr(rr)), "ls_gradient")
+        return c, rr
+
+    def gradient_noalloc(self, A: torch.Tensor, b: torch.Tensor, x: torch.Tensor, c: torch.Tensor,
+                         rr: torch.Tensor | None = None):
+        """ls_gradient_noalloc: the same c and ||r||^2 into caller-given buffers, with the library's
+        fixed per-GPU scratch in place of its workspace."""
+        m, n, lda = _mat(A, "A")
+        if c.numel() != n:
+            raise ValueError("c: need n entries")
+        self._check(self._L.ls_gradient_noalloc(self.h, self._stream(), m, n, _ptr(A), lda,
+                                                _ptr(_vec(b, "b")), _ptr(_vec(x, "x")),
+                                                _ptr(_vec(c, "c")),
+                                                _ptr(None if rr is None else _vec(rr, "rr"))),
+                    "ls_gradient_noalloc")
         return c, rr
 
     # (a8) d = R^{-1} R^{-T} c

@@ -139,6 +139,11 @@ def test_qr_gradient_solve_argument_errors(L, hctx):
     assert L.ls_gradient(hctx, S0, 100, 10, P, 10, P, P, P, NUL) == ls.LS_ERR_DEVICE
     assert L.ls_gradient(hctx, S0, 0, 10, P, 10, P, P, P, NUL) == ls.LS_ERR_ARG
     assert L.ls_gradient(hctx, S0, 100, 10, P, 10, P, NUL, P, NUL) == ls.LS_ERR_ARG
+    # the allocation-free form validates alike, then needs a device
+    assert L.ls_gradient_noalloc(hctx, S0, 100, 10, P, 10, P, P, P, NUL) == ls.LS_ERR_DEVICE
+    assert L.ls_gradient_noalloc(hctx, S0, 0, 10, P, 10, P, P, P, NUL) == ls.LS_ERR_ARG
+    assert L.ls_gradient_noalloc(hctx, S0, 100, 10, P, 9, P, P, P, NUL) == ls.LS_ERR_ARG
+    assert L.ls_gradient_noalloc(hctx, S0, 100, 4096, P, 4096, P, P, P, NUL) == ls.LS_ERR_UNSUPPORTED
     assert L.ls_precond_solve(hctx, S0, 10, P, 10, P, P) == ls.LS_ERR_DEVICE
     assert L.ls_precond_solve(hctx, S0, 10, P, 5, P, P) == ls.LS_ERR_ARG
     assert L.ls_iterate(hctx, S0, 100, 10, P, 10, P, P, 10, P, 3, NUL) == ls.LS_ERR_DEVICE
