@@ -4,9 +4,12 @@ A step is one complete solve (sparse-sign sketch of A, Householder QR of the ske
 solve start and q refinement passes) of the synthetic problem m = 2,000,000, n = 500, d = 10,000,
 zeta = 8, q = 40, kappa = 1e10, ||r|| = 1e-6, with A and b already resident in HBM.  It prints one
 JSON line: solves/s, the fused pass's achieved HBM bandwidth against the 8 TB/s peak (per-launch
-kernel time from HIP events on the launch stream), and the CPU oracle timed on a bounded sample.
+kernel time from HIP events on the launch stream), and the CPU oracle (Householder least squares in
+TSQR form, on every host thread and on one) timed on a bounded sample of the same A and b.  The line
+also carries a bounded sub-record ("large") of the largest workload: m = 4,000,000, n = 2000
+(A = 64 GB), d = 40,000, q = 40, one warm-up and --large-steps timed FP64 solves.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--large-steps 2]
 
 Other workloads (one JSON line each):
     --workload mixed_m1e6_n1000   mixed precision (FP32 sketch/QR/R-solves, FP64 pass/update) against
@@ -70,36 +73,117 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w: dict, sample_rows: int):
-    """The oracle's Algorithm 2 on a bounded sample of the workload, scaled to solves/s.
+def host_cpu():
+    """(threads this process may use, nproc, CPU model from lscpu)."""
+    import subprocess
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return len(os.sched_getaffinity(0)), os.cpu_count(), model
 
-    Sample: the sketch and one refinement pass on the first `sample_rows` rows of a problem of the
-    workload's shape (both linear in m), and the Householder QR of that sample's d x n sketch
-    (independent of m).  Estimated solve time = (m / rows) * (t_sketch + q t_pass) + t_qr."""
-    import numpy as np
 
+def median_time(fn, reps: int = 3) -> float:
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline(w: dict, Ah, bh, copy_s: float, rows_all: int, rows_one: int):
+    """The oracle timed on the host's cores on a bounded sample of the workload itself.
+
+    Primary: Householder least squares in TSQR form (the oracle's backward-stable solver) on the
+    first rows of the benchmark's own A and b (copied from the GPU beforehand; the copy is timed
+    apart), on every host thread this process may use and on one, median of 3 runs each.  Its work
+    (2 m n^2 flops) is linear in m for m >> n, so a sample of r rows scales by m / r.
+    Second: the oracle's Algorithm 2 (sketch, Householder QR of the sketch, one refinement pass on
+    the sample, scaled like the GPU solve: (m / r)(t_sketch + q t_pass) + t_qr), one thread."""
     import oracle
-    from synth import ProblemSpec, make_problem_cpu
 
     m, n, d, q = w["m"], w["n"], w["d"], w["q"]
-    rows = min(sample_rows, m)
-    p = make_problem_cpu(ProblemSpec(m=rows, n=n, kappa=w["kappa"], beta=w["beta"], d=d, seed=0))
-    A, b = np.ascontiguousarray(p.A[:, :n]), p.b
+    threads, nproc, model = host_cpu()
+    A1, b1 = Ah[:rows_all], bh[:rows_all]
+    A2, b2 = Ah[:rows_one], bh[:rows_one]
+    t_all = median_time(lambda: oracle.tsqr_lstsq(A1, b1, block_rows=8192, threads=threads))
+    t_one = median_time(lambda: oracle.tsqr_lstsq(A2, b2, block_rows=8192, threads=1))
+    s_all = t_all * m / rows_all
+    s_one = t_one * m / rows_one
+    # second baseline: Algorithm 2 on the oracle, one thread
     t0 = time.perf_counter()
-    B, Sb = oracle.sketch(A, b, n, d, w["zeta"], p.spec.sketch_seed)
+    B, Sb = oracle.sketch(A1, b1, n, d, w["zeta"], 0)
     t1 = time.perf_counter()
     x0, R, _, _ = oracle.householder_lstsq(B, Sb)
     t2 = time.perf_counter()
-    c, _ = oracle.residual_gradient(A, b, x0)
+    c, _ = oracle.residual_gradient(A1, b1, x0)
     oracle.solve_r(R, oracle.solve_rt(R, c))
     t3 = time.perf_counter()
-    scale = m / rows
-    t_solve = scale * (t1 - t0) + (t2 - t1) + q * scale * (t3 - t2)
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle (plain C, 1 thread) sketch + 1 refinement pass on {rows} of {m} rows "
-                       f"scaled by m/rows, plus Householder QR of the {d}x{n} sketch; "
-                       f"t_sketch={t1 - t0:.2f}s t_qr={t2 - t1:.2f}s t_pass={t3 - t2:.3f}s "
-                       f"-> {t_solve:.1f} s/solve")}
+    s_alg2 = (m / rows_all) * ((t1 - t0) + q * (t3 - t2)) + (t2 - t1)
+    return {"value": 1.0 / s_all, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"Householder least squares (TSQR form, 8192-row blocks) on the first {rows_all} "
+                       f"of {m} rows of the benchmark's A and b, {threads} threads, median of 3: "
+                       f"{t_all:.2f} s, scaled by m/rows to {s_all:.1f} s/solve"),
+            "cpu_model": model, "nproc": nproc,
+            "single_thread": {"value": 1.0 / s_one, "unit": "solves/s", "cores": 1,
+                              "sample": f"the same on the first {rows_one} rows, 1 thread, median of 3: "
+                                        f"{t_one:.2f} s, scaled to {s_one:.1f} s/solve"},
+            "host_copy_s": copy_s,
+            "algorithm2_oracle": {"value": 1.0 / s_alg2, "unit": "solves/s", "cores": 1,
+                                  "sample": (f"the oracle's Algorithm 2 (sketch + 1 refinement pass) on "
+                                             f"{rows_all} rows scaled by m/rows, plus Householder QR of "
+                                             f"the {d}x{n} sketch; t_sketch={t1 - t0:.2f}s "
+                                             f"t_qr={t2 - t1:.2f}s t_pass={t3 - t2:.3f}s")}}
+
+
+def bench_large_record(args, ls):
+    """A bounded run of the largest workload (m = 4e6, n = 2000, A = 64 GB): `steps` timed FP64
+    solves after one warm-up, with the fused pass's bandwidth from HIP events and the forward error."""
+    import torch
+
+    from synth import ProblemSpec, make_problem_gpu
+
+    w = WORKLOADS["ls_large_m4e6_n2000"]
+    m, n, d, q = w["m"], w["n"], w["d"], w["q"]
+    spec = ProblemSpec(m=m, n=n, kappa=w["kappa"], beta=w["beta"], d=d, q=q, zeta=w["zeta"], seed=0)
+    t_gen = time.perf_counter()
+    p = make_problem_gpu(spec)
+    print(f"[bench] generated ls_large_m4e6_n2000 on GPU in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    A, b = p.A[:, :n], p.b
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx = ls.Context(0)
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    ctx.set_option(ls.OPT_ZETA, w["zeta"])
+    ctx.solve(A, b, d, q, x)
+    torch.cuda.synchronize()
+    ctx.set_option(ls.OPT_PROFILE, 1)
+    ctx.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.large_steps):
+        ctx.solve(A, b, d, q, x)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.large_steps
+    pass_ms, launches = ctx.profile(reset=True)
+    per_launch = pass_ms / max(launches, 1)
+    gbs = pass_bytes(m, n) / (per_launch * 1e-3) / 1e9
+    fe = float(torch.linalg.norm(x - p.x_true).item())
+    del A, b, x, p
+    ctx.close()
+    release_device()
+    out = {"workload": "ls_large_m4e6_n2000", "m": m, "n": n, "d": d, "zeta": w["zeta"], "q": q,
+           "kappa": w["kappa"], "residual_norm": w["beta"], "dtype": "f64",
+           "steps": args.large_steps, "warmup": 1, "ms_per_step": 1e3 * t, "solves_per_s": 1.0 / t,
+           "pass_avg_launch_ms": per_launch, "pass_GBps": gbs, "pass_frac_of_8TBps": gbs / HBM_PEAK_GBS,
+           "forward_error": fe}
+    print(f"[bench] large: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def release_device():
@@ -236,19 +320,13 @@ def bench_large(args, w):
     print(json.dumps(rec), flush=True)
 
 
-def served_problems(w, seed=7):
-    """The request stream: shapes, conditioning and Poisson arrival times, seeded."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    out = []
-    t = 0.0
-    for i in range(w["count"]):
-        m = int(math.floor(math.exp(rng.uniform(math.log(w["m_lo"]), math.log(w["m_hi"])))))
-        n = int(rng.choice(w["ns"]))
-        kappa = math.exp(rng.uniform(math.log(w["kappa_lo"]), math.log(w["kappa_hi"])))
-        t += rng.exponential(1.0 / w["rate"])
-        out.append(dict(m=m, n=n, kappa=kappa, d=20 * n, arrival=t, seed=1000 + i))
-    return out
+def served_problems(w, seed=2311):
+    """The request stream: Poisson arrival times, shapes and conditioning from the master seed
+    (synth.served_stream); problem k is built from problem seed 1000 + k."""
+    from synth.problems import served_stream
+    t, ms, ns, kap = served_stream(count=w["count"], rate=w["rate"], seed=seed)
+    return [dict(m=int(ms[i]), n=int(ns[i]), kappa=float(kap[i]), d=20 * int(ns[i]), arrival=float(t[i]),
+                 seed=1000 + i) for i in range(w["count"])]
 
 
 def pct(v, q):
@@ -372,7 +450,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ls_fp64_m2e6_n500", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=500_000)
+    ap.add_argument("--cpu-sample-rows", type=int, default=400_000,
+                    help="rows of the all-threads oracle sample (the one-thread sample is a quarter)")
+    ap.add_argument("--large-steps", type=int, default=2,
+                    help="timed solves of the m = 4e6, n = 2000 sub-record (0: skip it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -467,14 +548,23 @@ def main():
                                    "bytes_written_per_copy": src.numel() * 8,
                                    "ms_per_copy": ms, "GB/s": moved / (ms * 1e-3) / 1e9}
         del src, dst
-    # Release the problem, the context's workspace, events and pinned word before the CPU work and
-    # well before interpreter shutdown: nothing of HIP's is left for exit-time destructors.
+    # The CPU oracle's sample: the first rows of this very A and b, copied to the host.
+    if not args.no_cpu_baseline:
+        rows = min(args.cpu_sample_rows, m)
+        t_copy = time.perf_counter()
+        Ah = A[:rows].cpu().numpy()
+        bh = b[:rows].cpu().numpy()
+        t_copy = time.perf_counter() - t_copy
+    # Release the problem, the context's workspace, events and pinned word before the next
+    # workload and well before interpreter shutdown.
     del A, b, x, p
     ctx.close()
     release_device()
+    if args.large_steps > 0:
+        rec["large"] = bench_large_record(args, ls)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_rows)
+        rec["cpu_baseline"] = cpu_baseline(w, Ah, bh, t_copy, rows, max(rows // 4, n + 1))
     print(json.dumps(rec), flush=True)
 
 

@@ -5,11 +5,22 @@
 #include <cstring>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.hpp"
 
 namespace {
 
 const char *kNullCtx = "null context";
+
+// A named host-side range around the enqueueing of one phase, for profilers that record roctx
+// markers (rocprofv3 --marker-trace); without such a profiler the calls do nothing.
+struct Range {
+    explicit Range(const char *name) { roctxRangePush(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -271,14 +282,21 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
         est_work = ar.take<double>((size_t)3 * (size_t)n);
     }));
     // (a) sketch straight into the QR work matrix: B in columns 0..n-1, S b in column n.
-    LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
-    const double scale = 1.0 / std::sqrt((double)zeta);
-    HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw, &sb.win), "gather kernel");
+    {
+        Range r("ls_solve: sketch");
+        LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
+        const double scale = 1.0 / std::sqrt((double)zeta);
+        HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb.W, qb.ldw, qb.W + n, qb.ldw, &sb.win), "gather kernel");
+    }
     // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
-    HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
-    HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
+    {
+        Range r("ls_solve: QR and x0");
+        HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1), "QR kernels");
+        HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
+        HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
+    }
     // (c) q refinement steps (with the stopping rule: at most q, ended on the device).
+    Range r("ls_solve: refinement");
     return iterate_fp64(ctx, s, m, n, A, lda, b, d, q, x, R, qb.RT, ib, est_work);
 }
 
@@ -324,6 +342,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
         est64 = ar.take<double>((size_t)3 * (size_t)n);
     }));
     // (a) FP64 sketch: B in the FP64 work matrix, S b contiguous; rounded copy for the FP32 QR.
+    Range r_all("ls_solve: mixed precision");
     LS_TRY(do_embedding(ctx, s, m, d, zeta, ctx->seed, sb, true));
     const double scale = 1.0 / std::sqrt((double)zeta);
     HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb64.W, qb64.ldw, Sb, 1, &sb.win), "gather kernel");
@@ -537,6 +556,7 @@ ls_status ls_sketch_embedding(ls_ctx *ctx, void *stream, int64_t m, int64_t d, i
                               uint64_t seed, int32_t *rows, int8_t *signs)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_sketch_embedding");
     LS_TRY(check_embedding(ctx, m, d, zeta));
     if (!rows || !signs || !aligned(rows, 4)) return ls_fail(ctx, LS_ERR_ARG, "rows/signs NULL or misaligned");
     LS_TRY(need_device(ctx));
@@ -553,6 +573,7 @@ ls_status ls_sketch_csr(ls_ctx *ctx, void *stream, int64_t m, int64_t d, int32_t
                         int32_t *rowptr, int32_t *cols)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_sketch_csr");
     LS_TRY(check_embedding(ctx, m, d, zeta));
     if (!rowptr || !cols || !aligned(rowptr, 4) || !aligned(cols, 4))
         return ls_fail(ctx, LS_ERR_ARG, "rowptr/cols NULL or misaligned");
@@ -572,6 +593,7 @@ ls_status ls_sketch(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doubl
                     double *Sb)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_sketch");
     LS_TRY(check_n(ctx, n));
     LS_TRY(check_embedding(ctx, m, d, zeta));
     LS_TRY(check_mat(ctx, A, lda, n, "A"));
@@ -594,6 +616,7 @@ ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const do
                        const double *Sb, double *R, int64_t ldr, double *x0)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_qr_sketch");
     LS_TRY(check_n(ctx, n));
     if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
     LS_TRY(check_mat(ctx, B, ldb, n, "B"));
@@ -616,6 +639,7 @@ ls_status ls_gradient(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const dou
                       const double *b, const double *x, double *c, double *rnorm2)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_gradient");
     LS_TRY(check_n(ctx, n));
     if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
     LS_TRY(check_mat(ctx, A, lda, n, "A"));
@@ -666,6 +690,7 @@ ls_status ls_precond_solve(ls_ctx *ctx, void *stream, int64_t n, const double *R
                            const double *c, double *d)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_precond_solve");
     LS_TRY(check_n(ctx, n));
     LS_TRY(check_mat(ctx, R, ldr, n, "R"));
     LS_TRY(check_vec(ctx, c, "c"));
@@ -691,6 +716,7 @@ ls_status ls_sketch_f32(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const d
                         float *Sb)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_sketch_f32");
     LS_TRY(check_n(ctx, n));
     LS_TRY(check_embedding(ctx, m, d, zeta));
     LS_TRY(check_mat(ctx, A, lda, n, "A"));
@@ -713,6 +739,7 @@ ls_status ls_qr_sketch_f32(ls_ctx *ctx, void *stream, int64_t d, int64_t n, cons
                            int64_t ldb, const float *Sb, float *R, int64_t ldr, double *x0)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_qr_sketch_f32");
     LS_TRY(check_n(ctx, n));
     if (d < n) return ls_fail(ctx, LS_ERR_ARG, "d must be >= n");
     LS_TRY(check_mat(ctx, B, ldb, n, "B", 4));
@@ -735,6 +762,7 @@ ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float
                                const double *c, double *d)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_precond_solve_f32");
     LS_TRY(check_n(ctx, n));
     LS_TRY(check_mat(ctx, R, ldr, n, "R", 4));
     LS_TRY(check_vec(ctx, c, "c"));
@@ -758,6 +786,7 @@ ls_status ls_iterate(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const doub
                      double *rnorm2)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_iterate");
     LS_TRY(check_n(ctx, n));
     if (m < 1) return ls_fail(ctx, LS_ERR_ARG, "m must be >= 1");
     if (q < 0) return ls_fail(ctx, LS_ERR_ARG, "q must be >= 0");
@@ -797,6 +826,7 @@ ls_status ls_solve(ls_ctx *ctx, void *stream, int64_t m, int64_t n, const double
                    const double *b, int64_t d, int32_t q, double *x)
 {
     if (!ctx) return LS_ERR_ARG;
+    Range range_("ls_solve");
     LS_TRY(check_n(ctx, n));
     if (m < n) return ls_fail(ctx, LS_ERR_ARG, "m must be >= n");
     if (d <= 0) d = dimension_rule(m, n);
