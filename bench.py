@@ -222,16 +222,21 @@ def bench_mixed(args, w):
     ctx.set_option(ls.OPT_ZETA, w["zeta"])
     x = torch.empty(n, dtype=torch.float64, device="cuda")
     cases, speedups_stop, speedups_q = [], [], []
-    for kappa in w["kappas"]:
-        for beta in w["betas"]:
+    kappas = [float(v) for v in args.kappas.split(",")] if args.kappas else list(w["kappas"])
+    betas = [float(v) for v in args.betas.split(",")] if args.betas else list(w["betas"])
+    precs = [(0, "fp64"), (1, "mixed")]
+    precs = [pn for pn in precs if pn[1] in args.precisions.split(",")]
+    modes = [md for md in ((1, w["qmax"], "stop"), (0, q, "q40")) if md[2] in args.modes.split(",")]
+    for kappa in kappas:
+        for beta in betas:
             spec = ProblemSpec(m=m, n=n, kappa=kappa, beta=beta, d=d, q=q, zeta=w["zeta"], seed=0)
             p = make_problem_gpu(spec)
             A, b = p.A[:, :n], p.b
             ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
             row = {"kappa": kappa, "residual_norm": beta}
-            for stop, qq, tag in ((1, w["qmax"], "stop"), (0, q, "q40")):
+            for stop, qq, tag in modes:
                 ctx.set_option(ls.OPT_STOP, stop)
-                for prec, name in ((0, "fp64"), (1, "mixed")):
+                for prec, name in precs:
                     ctx.set_option(ls.OPT_PRECISION, prec)
                     t, info = timed_solves(ctx, A, b, d, qq, x, args.steps)
                     fe = float(torch.linalg.norm(x - p.x_true).item())
@@ -241,10 +246,13 @@ def bench_mixed(args, w):
                                             "condest": info[3]}
             ctx.set_option(ls.OPT_PRECISION, 0)
             ctx.set_option(ls.OPT_STOP, 0)
-            row["speedup_stop"] = row["stop_fp64"]["ms"] / row["stop_mixed"]["ms"]
-            row["speedup_q40"] = row["q40_fp64"]["ms"] / row["q40_mixed"]["ms"]
-            speedups_stop.append(row["speedup_stop"])
-            speedups_q.append(row["speedup_q40"])
+            for tag, acc in (("stop", speedups_stop), ("q40", speedups_q)):
+                if f"{tag}_fp64" in row and f"{tag}_mixed" in row:
+                    row[f"speedup_{tag}"] = row[f"{tag}_fp64"]["ms"] / row[f"{tag}_mixed"]["ms"]
+                    acc.append(row[f"speedup_{tag}"])
+            brief = {k: (v["ms"], v["precision_used"], v["forward_error"]) for k, v in row.items()
+                     if isinstance(v, dict)}
+            print(f"[bench] kappa={kappa:.0e} r={beta:.0e}: {brief}", file=sys.stderr, flush=True)
             cases.append(row)
             print(f"[bench] kappa={kappa:.0e} r={beta:.0e}: stop fp64 {row['stop_fp64']['ms']:.1f} ms "
                   f"mixed {row['stop_mixed']['ms']:.1f} ms ({row['stop_mixed']['precision_used']}) "
@@ -252,18 +260,22 @@ def bench_mixed(args, w):
                   file=sys.stderr, flush=True)
             del p, A, b
             torch.cuda.empty_cache()
-    geo = math.exp(sum(math.log(v) for v in speedups_stop) / len(speedups_stop))
+    def geomean(v):
+        return math.exp(sum(math.log(t) for t in v) / len(v)) if v else None
+
+    geo = geomean(speedups_stop)
     rec = {
         "metric": "mixed/FP64 speedup at equal fwd error",
         "value": geo,
         "unit": "x (geometric mean over the nine cases, both with the Section 3.3 stopping rule)",
         "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": sum(c["stop_mixed"]["ms"] for c in cases) / len(cases),
+        "ms_per_step": (sum(c["stop_mixed"]["ms"] for c in cases) / len(cases)
+                        if all("stop_mixed" in c for c in cases) else None),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "d": d, "zeta": w["zeta"],
                    "qmax_stop": w["qmax"], "q_fixed": q},
-        "speedup_q40_geomean": math.exp(sum(math.log(v) for v in speedups_q) / len(speedups_q)),
+        "speedup_q40_geomean": geomean(speedups_q),
         "cases": cases,
     }
     ctx.close()
@@ -288,6 +300,8 @@ def bench_large(args, w):
     x = torch.empty(n, dtype=torch.float64, device="cuda")
     out = {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
+        if name not in args.precisions.split(","):
+            continue
         ctx.set_option(ls.OPT_PRECISION, prec)
         ctx.set_option(ls.OPT_PROFILE, 1)
         ctx.profile(reset=True)
@@ -301,18 +315,19 @@ def bench_large(args, w):
                      "pass_GBps": pass_bytes(m, n) / (per_launch * 1e-3) / 1e9}
         print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
     ctx.set_option(ls.OPT_PRECISION, 0)
-    achieved = out["fp64"]["pass_GBps"]
+    main = out["fp64"] if "fp64" in out else out["mixed"]
+    achieved = main["pass_GBps"]
     rec = {
         "metric": "solves/s + iteration-pass HBM GB/s; mixed/FP64 speedup at equal fwd error",
-        "value": out["fp64"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": 1, "ms_per_step": out["fp64"]["ms"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "value": main["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": main["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if "fp64" in out else "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "d": d, "zeta": w["zeta"], "q": q,
                    "kappa": w["kappa"], "residual_norm": w["beta"]},
         "roofline": {"bound": "hbm", "kernel": "k_pass (fused A^T(b - A x) pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "mixed": out["mixed"], "fp64": out["fp64"],
-        "mixed_speedup": out["fp64"]["ms"] / out["mixed"]["ms"],
+        **out,
+        "mixed_speedup": (out["fp64"]["ms"] / out["mixed"]["ms"]) if len(out) == 2 else None,
     }
     del p, A, b, x
     ctx.close()
@@ -390,9 +405,11 @@ def bench_served(args, w):
                 "rounds": stats["rounds"], "failed": sum(1 for s_ in status if s_ != ls.LS_OK),
                 "footprint_peak_GB": stats["footprint_peak"] / 1e9}, xs
 
-    def baseline(poisson: bool):
+    def baseline(poisson: bool, precision: int = 0):
         ctx = ls.Context(0)
         ctx.set_option(ls.OPT_ZETA, w["zeta"])
+        ctx.set_option(ls.OPT_PRECISION, precision)
+        used = []
         xs = []
         spec, A, b, _ = probs[0]
         ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
@@ -407,10 +424,16 @@ def bench_served(args, w):
             ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
             xs.append(ctx.solve(A, b, spec.d, q))      # waits for the result
             lat.append(time.perf_counter() - arrival)
+            used.append(ctx.solve_info()[4])
         t_end = time.perf_counter()
         ctx.close()
-        return {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
-                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99)}, xs
+        out = {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+               "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99)}
+        if precision:
+            names = ["fp64", "mixed", "fell_back_condest", "fell_back_growth"]
+            out["precision_used"] = {nm: sum(1 for u in used if u == k) for k, nm in enumerate(names)}
+            out["per_request"] = [{"n": r["n"], "kappa": r["kappa"], "used": names[u]} for r, u in zip(reqs, used)]
+        return out, xs
 
     out = {}
     out["served_saturation"], xs_sat = served(False)
@@ -421,6 +444,13 @@ def bench_served(args, w):
     print(f"[bench] ls_solve saturation: {out['ls_solve_saturation']}", file=sys.stderr, flush=True)
     out["ls_solve_poisson"], _ = baseline(True)
     print(f"[bench] ls_solve poisson: {out['ls_solve_poisson']}", file=sys.stderr, flush=True)
+    # The mixed-precision arm: the served stream runs FP64 only, so the mixed form is ls_solve with
+    # LS_OPT_PRECISION = 1, one request at a time, with the precision each request ended in.
+    out["ls_solve_mixed_saturation"], xs_mixed = baseline(False, precision=1)
+    print(f"[bench] ls_solve mixed saturation: "
+          f"{ {k: v for k, v in out['ls_solve_mixed_saturation'].items() if k != 'per_request'} }",
+          file=sys.stderr, flush=True)
+    fe_mixed = [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs_mixed, probs)]
     same = all(torch.equal(a, b_) for a, b_ in zip(xs_sat, xs_base))
     fe = [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs_sat, probs)]
     rec = {
@@ -436,9 +466,13 @@ def bench_served(args, w):
         "speedup_saturation_vs_ls_solve": out["served_saturation"]["solves_per_s"] / out["ls_solve_saturation"]["solves_per_s"],
         "bitwise_equal_to_ls_solve": same,
         "forward_error_max": max(fe),
+        "mixed_vs_fp64_ls_solve_speedup": (out["ls_solve_mixed_saturation"]["solves_per_s"]
+                                           / out["ls_solve_saturation"]["solves_per_s"]),
+        "forward_error_max_mixed": max(fe_mixed),
+        "forward_error_mixed_over_fp64_max": max(a / max(b_, 1e-300) for a, b_ in zip(fe_mixed, fe)),
         **out,
     }
-    del probs, xs_sat, xs_base
+    del probs, xs_sat, xs_base, xs_mixed
     release_device()
     print(json.dumps(rec), flush=True)
 
@@ -454,6 +488,12 @@ def main():
                     help="rows of the all-threads oracle sample (the one-thread sample is a quarter)")
     ap.add_argument("--large-steps", type=int, default=2,
                     help="timed solves of the m = 4e6, n = 2000 sub-record (0: skip it)")
+    ap.add_argument("--precisions", default="fp64,mixed",
+                    help="mixed and large workloads: which of fp64, mixed to run")
+    ap.add_argument("--kappas", default="", help="mixed workload: kappas to run (default: all three)")
+    ap.add_argument("--betas", default="", help="mixed workload: ||r|| values to run (default: all three)")
+    ap.add_argument("--modes", default="stop,q40",
+                    help="mixed workload: stop (Section 3.3 rule, q <= 200) and/or q40 (fixed q)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
     args = ap.parse_args()

@@ -216,8 +216,12 @@ ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float
 /* ---- Served stream (many independent solves resident on one GPU) -------------------------------
  * A server solves submitted problems with ls_solve's FP64 algorithm (zeta = 8, fixed q, plain update)
  * and returns, for each, the same bits ls_solve returns for it alone.  Problems are admitted first
- * in, first out while the sum of the footprints 8mn + 8m + 8n^2 + 4 zeta m + 8dn of the admitted
- * problems stays within `budget_bytes` and at most `max_active` are admitted; the sketch, QR and
+ * in, first out while the footprint stays within `budget_bytes` and at most `max_active` are
+ * admitted.  The footprint counts, for every admitted problem, its resident bytes (A and b, 8mn + 8m,
+ * plus its device block: R, R^T, pass partials, c) and the workspaces the four setup lanes hold
+ * (embedding, lists, sketch and QR work matrix of the largest problem each set up; an idle lane
+ * gives its workspace back when the next problem would not fit otherwise); ls_server_footprint
+ * reports both figures for a shape.  The sketch, QR and
  * start of each are computed on one of four setup streams (four problems at a time), then every
  * admitted problem takes one refinement step per round on a serve stream (one batched launch per
  * kernel for all of them: continuous batching -- problems join and leave between rounds).  A
@@ -230,8 +234,15 @@ typedef struct ls_server ls_server;
 ls_status ls_server_create(int device, int64_t budget_bytes, int32_t max_active, ls_server **out);
 /* Finishes every submitted request, then frees the server. */
 void ls_server_destroy(ls_server *server);
+/* What admission charges for a problem of this shape: *resident (bytes held while it is admitted)
+ * and *setup (the setup-lane workspace its sketch and QR need).  A problem is refused at submission
+ * (LS_ERR_ALLOC) when resident + setup exceeds the budget. */
+ls_status ls_server_footprint(ls_server *server, int64_t m, int64_t n, int64_t d, int64_t *resident,
+                              int64_t *setup);
 /* Queues one solve (arguments as ls_solve; d >= n) and returns its ticket.  LS_ERR_ALLOC if its
- * footprint alone exceeds the budget.  Never blocks on the device. */
+ * footprint alone exceeds the budget.  Never blocks on the device.  A finished request keeps only a
+ * small host record (result and times) until the server is destroyed; its event and pinned status
+ * word are reused by later requests. */
 ls_status ls_server_submit(ls_server *server, int64_t m, int64_t n, const double *A, int64_t lda,
                            const double *b, int64_t d, int32_t q, uint64_t seed, double *x,
                            int64_t *ticket);
@@ -241,8 +252,8 @@ ls_status ls_server_wait(ls_server *server, int64_t ticket, double timeout_s, ls
 /* times[0..3]: submission, admission, first round, completion (seconds since ls_server_create;
  * completion is when the scheduler saw the last round end). */
 ls_status ls_server_request_info(ls_server *server, int64_t ticket, double *times);
-/* stats[0..6]: submitted, finished, queued, admitted and unfinished, footprint now, peak footprint,
- * rounds launched. */
+/* stats[0..7]: submitted, finished, queued, admitted and unfinished, footprint now, peak footprint,
+ * rounds launched, bytes of the footprint held by the setup lanes' workspaces. */
 ls_status ls_server_stats(ls_server *server, int64_t *stats);
 const char *ls_server_last_error(ls_server *server);
 

@@ -39,7 +39,8 @@ struct Req {
     uint64_t seed = 0;
     const double *A = nullptr, *b = nullptr;
     double *x = nullptr;
-    int64_t footprint = 0;
+    int64_t footprint = 0;             // resident bytes (resident_bytes)
+    int64_t setup = 0;                 // setup-lane workspace it needs (setup_bytes)
     St st = St::Queued;
     int32_t rounds = 0;
     double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
@@ -90,7 +91,10 @@ struct ls_server {
     // device memory cache (blocks are reused, released at destroy)
     std::vector<std::pair<size_t, void *>> free_blocks;
     std::vector<void *> all_blocks;
-    std::vector<int32_t *> pinned_status;
+    std::vector<int32_t *> pinned_status;   // every pinned status word made (freed at destroy)
+    std::vector<int32_t *> pin_pool;        // status words of finished requests, for reuse
+    std::vector<hipEvent_t> ev_pool;        // events of finished requests, for reuse
+    int64_t lanes_ws = 0;                   // bytes held by the setup lanes' workspaces
     // requests
     std::mutex mu;
     std::condition_variable cv_done, cv_work;
@@ -112,11 +116,39 @@ namespace {
 
 double seconds_since(const ls_server *sv) { return std::chrono::duration<double>(Clock::now() - sv->t0).count(); }
 
-// Footprint of a resident problem (bytes): A and b, R, the embedding and the sketch while it is set
-// up -- 8 m n + 8 m + 8 n^2 + 4 zeta m + 8 d n.
-int64_t footprint(int64_t m, int64_t n, int64_t d, int32_t zeta)
+// The per-problem device block (R, R^T, pass partials, c, ||r||^2, status word), carved from `base`
+// (nullptr: sizing only).  Returns its size in bytes.
+size_t carve_req(Req *r, char *base)
 {
-    return 8 * m * n + 8 * m + 8 * n * n + 4 * (int64_t)zeta * m + 8 * d * n;
+    Arena ar;
+    ar.base = base;
+    r->R = ar.take<double>((size_t)(r->n * r->n));
+    r->RT = ar.take<double>((size_t)(r->n * r->n));
+    r->part = ar.take<double>((size_t)r->P * (size_t)r->n);
+    r->part_rr = ar.take<double>((size_t)r->P);
+    r->c = ar.take<double>((size_t)r->n);
+    r->rr = ar.take<double>(1);
+    r->status = ar.take<int32_t>(1);
+    return ar.off + 256;
+}
+
+// Bytes a problem holds while resident: its A and b (the caller's, but kept on the device while it
+// is served) and its device block.
+int64_t resident_bytes(Req *r)
+{
+    r->P = iter_partials(r->m, r->n);
+    return 8 * r->m * r->n + 8 * r->m + (int64_t)carve_req(r, nullptr);
+}
+
+// Workspace a setup lane needs for the sketch and QR of a problem (the same carve enqueue_setup makes).
+int64_t setup_bytes(int64_t m, int64_t n, int64_t d, int32_t zeta)
+{
+    SketchBufs sb{};
+    QrBufs qb{};
+    Arena ar;
+    sketch_bufs(ar, m, d, zeta, sb);
+    qr_bufs(ar, d, n, qb);
+    return (int64_t)ar.off + 256;
 }
 
 bool hip_ok(ls_server *sv, hipError_t e, const char *what)
@@ -155,40 +187,43 @@ void give_block(ls_server *sv, void *p, size_t bytes)
 bool alloc_req(ls_server *sv, Req *r)
 {
     r->P = iter_partials(r->m, r->n);
-    Arena sizing;
-    auto carve = [&](Arena &ar) {
-        r->R = ar.take<double>((size_t)(r->n * r->n));
-        r->RT = ar.take<double>((size_t)(r->n * r->n));
-        r->part = ar.take<double>((size_t)r->P * (size_t)r->n);
-        r->part_rr = ar.take<double>((size_t)r->P);
-        r->c = ar.take<double>((size_t)r->n);
-        r->rr = ar.take<double>(1);
-        r->status = ar.take<int32_t>(1);
-    };
-    carve(sizing);
-    r->mem_bytes = sizing.off + 256;
+    r->mem_bytes = carve_req(r, nullptr);
     r->mem = take_block(sv, r->mem_bytes);
     if (!r->mem) return false;
-    Arena real;
-    real.base = static_cast<char *>(r->mem);
-    carve(real);
+    carve_req(r, static_cast<char *>(r->mem));
     return true;
 }
 
-// A lane's workspace large enough for the sketch and QR of one problem (the lane is idle here).
-bool ensure_setup_ws(ls_server *sv, ls_server::Lane &ln, size_t bytes)
+// Frees an idle lane's workspace (its stream is drained first) and stops charging it.
+void release_lane_ws(ls_server *sv, ls_server::Lane &ln)
 {
-    if (bytes <= ln.ws_bytes) return true;
-    if (!hip_ok(sv, hipStreamSynchronize(ln.s), "setup stream synchronize")) return false;
-    if (ln.ws) (void)hipFree(ln.ws);
+    if (!ln.ws) return;
+    (void)hip_ok(sv, hipStreamSynchronize(ln.s), "setup stream synchronize");
+    (void)hipFree(ln.ws);
+    sv->lanes_ws -= (int64_t)ln.ws_bytes;
+    sv->footprint_now -= (int64_t)ln.ws_bytes;
     ln.ws = nullptr;
     ln.ws_bytes = 0;
-    if (hipMalloc(&ln.ws, bytes + bytes / 4) != hipSuccess) {
+}
+
+// A lane's workspace large enough for the sketch and QR of one problem (the lane is idle here).
+// The workspace is charged to the footprint; `room` is what the budget still allows beyond the
+// lane's present workspace, and growth takes a quarter of slack only where it fits.
+bool ensure_setup_ws(ls_server *sv, ls_server::Lane &ln, size_t bytes, int64_t room)
+{
+    if (bytes <= ln.ws_bytes) return true;
+    release_lane_ws(sv, ln);
+    size_t want = bytes + bytes / 4;
+    if ((int64_t)want > room) want = bytes;
+    if (hipMalloc(&ln.ws, want) != hipSuccess) {
         (void)hipGetLastError();
         ln.ws = nullptr;
         return false;
     }
-    ln.ws_bytes = bytes + bytes / 4;
+    ln.ws_bytes = want;
+    sv->lanes_ws += (int64_t)want;
+    sv->footprint_now += (int64_t)want;
+    sv->footprint_peak = std::max(sv->footprint_peak, sv->footprint_now);
     return true;
 }
 
@@ -197,6 +232,23 @@ int free_lane(const ls_server *sv)
     for (size_t i = 0; i < sv->lanes.size(); ++i)
         if (!sv->lanes[i].busy) return (int)i;
     return -1;
+}
+
+// The idle lane for a setup needing `need` bytes of workspace: the smallest workspace that holds it,
+// else the largest one (least growth); -1 if every lane is busy.
+int pick_lane(const ls_server *sv, int64_t need)
+{
+    int best = -1;
+    for (size_t i = 0; i < sv->lanes.size(); ++i) {
+        const auto &ln = sv->lanes[i];
+        if (ln.busy) continue;
+        if (best < 0) { best = (int)i; continue; }
+        const int64_t wb = (int64_t)sv->lanes[best].ws_bytes, wi = (int64_t)ln.ws_bytes;
+        const bool fits_b = wb >= need, fits_i = wi >= need;
+        if (fits_i && (!fits_b || wi < wb)) best = (int)i;
+        else if (!fits_i && !fits_b && wi > wb) best = (int)i;
+    }
+    return best;
 }
 
 // Enqueue sketch, QR, R, R^T and x_0 of one problem on a free setup lane (as ls_solve does), then the
@@ -213,7 +265,8 @@ bool enqueue_setup(ls_server *sv, Req *r, int lane)
     };
     Arena sizing;
     carve(sizing);
-    if (!ensure_setup_ws(sv, ln, sizing.off + 256)) {
+    const int64_t room = sv->budget - sv->footprint_now + (int64_t)ln.ws_bytes;
+    if (!ensure_setup_ws(sv, ln, sizing.off + 256, room)) {
         r->result = LS_ERR_ALLOC;
         return false;
     }
@@ -247,8 +300,10 @@ ls_status status_of(int32_t st)
     return LS_OK;
 }
 
-// Called with the lock held: a request leaves the server.
-void finish(ls_server *sv, Req *r, ls_status result)
+// Called with the lock held: a request leaves the server.  Its device block goes back to the cache;
+// with `recycle` (no device work of the request can still be pending) its event and pinned status
+// word go back to the pools for later requests.  Only the host record (result and times) stays.
+void finish(ls_server *sv, Req *r, ls_status result, bool recycle = true)
 {
     r->result = result;
     r->st = St::Done;
@@ -258,6 +313,12 @@ void finish(ls_server *sv, Req *r, ls_status result)
     sv->footprint_now -= r->footprint;
     sv->admitted_live -= 1;
     sv->completed += 1;
+    if (recycle) {
+        if (r->ev) sv->ev_pool.push_back(r->ev);
+        if (r->status_host) sv->pin_pool.push_back(r->status_host);
+        r->ev = nullptr;
+        r->status_host = nullptr;
+    }
     sv->cv_done.notify_all();
 }
 
@@ -336,17 +397,35 @@ void scheduler(ls_server *sv)
     for (;;) {
         bool progress = false;
         if (sv->fatal != LS_OK) {             // fail everything still pending
-            for (auto &kv : sv->reqs)
-                if (kv.second->st != St::Done) finish(sv, kv.second.get(), sv->fatal);
+            for (auto &kv : sv->reqs)     // device work may still be pending: keep their events
+                if (kv.second->st != St::Done) finish(sv, kv.second.get(), sv->fatal, false);
             sv->queue.clear();
             sv->setup.clear();
             sv->active.clear();
             sv->finishing.clear();
         }
-        // (1) admission: FIFO while the footprint budget, the slot table and a setup lane allow
-        while (!sv->queue.empty() && sv->admitted_live < sv->max_active && free_lane(sv) >= 0 &&
-               sv->footprint_now + sv->queue.front()->footprint <= sv->budget) {
+        // (1) admission: FIFO while the footprint budget, the slot table and a setup lane allow.
+        // The footprint counts every resident problem and the setup lanes' workspaces; a problem
+        // is admitted when its resident bytes and its lane's workspace growth fit the budget.  When
+        // the front problem does not fit, idle lanes give their workspaces back first.
+        while (!sv->queue.empty() && sv->admitted_live < sv->max_active && free_lane(sv) >= 0) {
             Req *r = sv->queue.front();
+            const int lane = pick_lane(sv, r->setup);
+            const int64_t grow = std::max<int64_t>(0, r->setup - (int64_t)sv->lanes[lane].ws_bytes);
+            if (sv->footprint_now + r->footprint + grow > sv->budget) {
+                bool freed = false;
+                for (auto &ln : sv->lanes)
+                    if (!ln.busy && ln.ws && &ln != &sv->lanes[lane]) {
+                        release_lane_ws(sv, ln);
+                        freed = true;
+                    }
+                if (freed) continue;
+                if (sv->lanes[lane].ws && grow > 0) {        // start the lane afresh at this size
+                    release_lane_ws(sv, sv->lanes[lane]);
+                    continue;
+                }
+                break;
+            }
             sv->queue.pop_front();
             r->t_admit = seconds_since(sv);
             if (!alloc_req(sv, r)) {
@@ -354,13 +433,16 @@ void scheduler(ls_server *sv)
                 r->st = St::Done;
                 r->t_done = r->t_admit;
                 sv->completed += 1;
+                if (r->ev) sv->ev_pool.push_back(r->ev);
+                if (r->status_host) sv->pin_pool.push_back(r->status_host);
+                r->ev = nullptr;
+                r->status_host = nullptr;
                 sv->cv_done.notify_all();
                 continue;
             }
             sv->footprint_now += r->footprint;
             sv->footprint_peak = std::max(sv->footprint_peak, sv->footprint_now);
             sv->admitted_live += 1;
-            const int lane = free_lane(sv);
             if (!enqueue_setup(sv, r, lane)) {
                 finish(sv, r, r->result != LS_OK ? r->result : LS_ERR_DEVICE);
                 continue;
@@ -552,6 +634,7 @@ void ls_server_destroy(ls_server *sv)
         for (auto &kv : sv->reqs) {
             if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
         }
+        for (hipEvent_t e : sv->ev_pool) (void)hipEventDestroy(e);
         for (int32_t *p : sv->pinned_status) (void)hipHostFree(p);
         for (void *p : sv->all_blocks) (void)hipFree(p);
         for (auto &st : sv->stage) {
@@ -581,10 +664,16 @@ ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A,
         const ls_status st = check_solve_args(sv, m, n, A, lda, b, d, q, x);
         if (st != LS_OK) return st;
     }
-    const int64_t fp = footprint(m, n, d, sv->zeta);
+    auto r = std::unique_ptr<Req>(new (std::nothrow) Req);
+    if (!r) return LS_ERR_ALLOC;
+    r->m = m;
+    r->n = n;
+    r->d = d;
+    const int64_t fp = (sv->device >= 0) ? resident_bytes(r.get()) : 8 * m * n + 8 * m;
+    const int64_t su = setup_bytes(m, n, d, sv->zeta);
     std::unique_lock<std::mutex> lk(sv->mu);
-    if (fp > sv->budget) {
-        sv->err = "the problem's footprint exceeds the server's HBM budget";
+    if (fp + su > sv->budget) {
+        sv->err = "the problem's footprint (resident bytes and setup workspace) exceeds the server's HBM budget";
         return LS_ERR_ALLOC;
     }
     if (sv->device < 0) {
@@ -592,30 +681,37 @@ ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A,
         return LS_ERR_DEVICE;
     }
     if (sv->fatal != LS_OK) return sv->fatal;
-    auto r = std::unique_ptr<Req>(new (std::nothrow) Req);
-    if (!r) return LS_ERR_ALLOC;
     int32_t *pin = nullptr;
-    if (hipHostMalloc(&pin, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    if (!sv->pin_pool.empty()) {
+        pin = sv->pin_pool.back();
+        sv->pin_pool.pop_back();
+    } else if (hipHostMalloc(&pin, sizeof(int32_t), hipHostMallocDefault) == hipSuccess) {
+        sv->pinned_status.push_back(pin);
+    } else {
         (void)hipGetLastError();
-        if (pin) (void)hipHostFree(pin);
-        sv->err = "cannot allocate the request's pinned status word or event";
+        sv->err = "cannot allocate the request's pinned status word";
         return LS_ERR_DEVICE;
     }
-    sv->pinned_status.push_back(pin);
+    if (!sv->ev_pool.empty()) {
+        r->ev = sv->ev_pool.back();
+        sv->ev_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        sv->pin_pool.push_back(pin);
+        sv->err = "cannot create the request's event";
+        return LS_ERR_DEVICE;
+    }
     *pin = 0;
     r->status_host = pin;
     r->ticket = sv->next_ticket++;
-    r->m = m;
-    r->n = n;
     r->lda = lda;
-    r->d = d;
     r->q = q;
     r->seed = seed;
     r->A = A;
     r->b = b;
     r->x = x;
     r->footprint = fp;
+    r->setup = su;
     r->t_submit = seconds_since(sv);
     *ticket = r->ticket;
     sv->queue.push_back(r.get());
@@ -640,6 +736,21 @@ ls_status ls_server_wait(ls_server *sv, int64_t ticket, double timeout_s, ls_sta
     if (timeout_s < 0) sv->cv_done.wait(lk, done);
     else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) return LS_ERR_TIMEOUT;
     if (result) *result = r->result;
+    return LS_OK;
+}
+
+ls_status ls_server_footprint(ls_server *sv, int64_t m, int64_t n, int64_t d, int64_t *resident,
+                              int64_t *setup)
+{
+    if (!sv || !resident || !setup) return LS_ERR_ARG;
+    if (n < 1 || n > LS_MAX_N || m < n || d < n || d >= (int64_t(1) << 31) || m * (int64_t)sv->zeta >= (int64_t(1) << 31))
+        return LS_ERR_ARG;
+    Req r;
+    r.m = m;
+    r.n = n;
+    r.d = d;
+    *resident = (sv->device >= 0) ? resident_bytes(&r) : 8 * m * n + 8 * m;
+    *setup = setup_bytes(m, n, d, sv->zeta);
     return LS_OK;
 }
 
@@ -668,6 +779,7 @@ ls_status ls_server_stats(ls_server *sv, int64_t *stats)
     stats[4] = sv->footprint_now;
     stats[5] = sv->footprint_peak;
     stats[6] = sv->rounds;
+    stats[7] = sv->lanes_ws;
     return LS_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_opti
            "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32",
            "ls_server_create", "ls_server_destroy", "ls_server_submit", "ls_server_wait",
            "ls_server_request_info", "ls_server_stats", "ls_server_last_error",
-           "ls_gradient_noalloc"]
+           "ls_gradient_noalloc", "ls_server_footprint"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -85,6 +85,7 @@ def load():
         "ls_server_request_info": ([_vp, _i64, ctypes.POINTER(_f64)], ctypes.c_int),
         "ls_server_stats": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
         "ls_server_last_error": ([_vp], ctypes.c_char_p),
+        "ls_server_footprint": ([_vp, _i64, _i64, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -339,10 +340,18 @@ class Server:
         return tuple(t)
 
     def stats(self):
-        s = (_i64 * 7)()
+        s = (_i64 * 8)()
         self._check(self._L.ls_server_stats(self.h, s), "ls_server_stats")
-        keys = ["submitted", "finished", "queued", "admitted", "footprint", "footprint_peak", "rounds"]
+        keys = ["submitted", "finished", "queued", "admitted", "footprint", "footprint_peak", "rounds",
+                "setup_workspace"]
         return dict(zip(keys, list(s)))
+
+    def footprint(self, m: int, n: int, d: int):
+        """(resident bytes, setup-lane workspace bytes) admission charges for a problem of this shape."""
+        res, su = _i64(), _i64()
+        self._check(self._L.ls_server_footprint(self.h, m, n, d, ctypes.byref(res), ctypes.byref(su)),
+                    "ls_server_footprint")
+        return res.value, su.value
 
 
 def limits():

@@ -227,7 +227,14 @@ def test_server_argument_errors(L):
         assert b"budget" in L.ls_server_last_error(h)
         res = ctypes.c_int()
         assert L.ls_server_wait(h, 12345, 0.0, ctypes.byref(res)) == ls.LS_ERR_ARG   # unknown ticket
-        st = (ctypes.c_int64 * 7)()
-        assert L.ls_server_stats(h, st) == ls.LS_OK and st[0] == 0
+        st = (ctypes.c_int64 * 8)()
+        assert L.ls_server_stats(h, st) == ls.LS_OK and st[0] == 0 and st[7] == 0
+        res_b, su_b = ctypes.c_int64(), ctypes.c_int64()
+        assert L.ls_server_footprint(h, 1000, 10, 200, ctypes.byref(res_b), ctypes.byref(su_b)) == ls.LS_OK
+        # host-only: A and b; the setup workspace holds at least the QR work matrix and the embedding
+        assert res_b.value == 8 * 1000 * 10 + 8 * 1000
+        assert su_b.value >= 8 * 200 * 11 + 4 * 8 * 1000
+        assert L.ls_server_footprint(h, 1000, 10, 9, ctypes.byref(res_b), ctypes.byref(su_b)) == ls.LS_ERR_ARG
+        assert L.ls_server_footprint(h, 1000, 10, 200, None, ctypes.byref(su_b)) == ls.LS_ERR_ARG
     finally:
         L.ls_server_destroy(h)

@@ -64,7 +64,8 @@ def test_served_equals_ls_solve_bitwise(ctx, probs, q):
             assert srv.wait(t, 120.0) == ls.LS_OK
             assert torch.equal(x, r)
         st = srv.stats()
-        assert st["finished"] == len(probs) and st["admitted"] == 0 and st["footprint"] == 0
+        assert st["finished"] == len(probs) and st["admitted"] == 0
+        assert st["footprint"] == st["setup_workspace"] > 0     # only the setup lanes' workspaces remain
         if q > 1:
             assert st["rounds"] < q * len(probs)          # rounds were shared
     finally:
@@ -93,9 +94,18 @@ def test_served_alone_vs_mixed_bitwise(probs):
 
 def test_admission_budget_limits_footprint(ctx, probs):
     ref = alone_results(ctx, probs, 12)
-    fps = [8 * p.spec.m * p.spec.n + 8 * p.spec.m + 8 * p.spec.n ** 2 + 32 * p.spec.m + 8 * p.spec.d * p.spec.n
-           for _, _, _, p in probs]
-    budget = max(fps) + min(fps)                            # at most two problems at a time
+    probe = ls.Server(-1)
+    host_fp = [probe.footprint(spec.m, spec.n, spec.d) for spec, _, _, _ in probs]
+    probe.close()
+    srv = ls.Server(0, budget_bytes=1 << 40, max_active=8)
+    fps = [srv.footprint(spec.m, spec.n, spec.d) for spec, _, _, _ in probs]
+    srv.close()
+    # the resident bytes count at least A and b; the setup workspace at least the sketch and its QR
+    for (spec, _, _, _), (res, su), (hres, hsu) in zip(probs, fps, host_fp):
+        assert res >= 8 * spec.m * spec.n + 8 * spec.m + 16 * spec.n ** 2
+        assert su >= 8 * spec.d * (spec.n + 1) + 4 * 8 * spec.m and su == hsu
+    # room for the largest problem with its setup, and the smallest besides: at most a few at a time
+    budget = max(r + s for r, s in fps) + min(r for r, _ in fps)
     srv = ls.Server(0, budget_bytes=budget, max_active=8)
     try:
         tk = [srv.submit(A, b, spec.d, 12, spec.sketch_seed) for spec, A, b, _ in probs]
