@@ -161,13 +161,19 @@ def bench_large_record(args, ls):
     ctx = ls.Context(0)
     ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
     ctx.set_option(ls.OPT_ZETA, w["zeta"])
+    ctx.set_option(ls.OPT_QR_PANEL, args.qr_panel)
     ctx.solve(A, b, d, q, x)
     torch.cuda.synchronize()
+    if args.verbose:
+        print("[bench] large: warm-up solve done", file=sys.stderr, flush=True)
     ctx.set_option(ls.OPT_PROFILE, 1)
     ctx.profile(reset=True)
     t0 = time.perf_counter()
-    for _ in range(args.large_steps):
+    for k in range(args.large_steps):
         ctx.solve(A, b, d, q, x)
+        if args.verbose:
+            torch.cuda.synchronize()
+            print(f"[bench] large: timed solve {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / args.large_steps
     pass_ms, launches = ctx.profile(reset=True)
@@ -220,6 +226,7 @@ def bench_mixed(args, w):
     m, n, d, q = w["m"], w["n"], w["d"], w["q"]
     ctx = ls.Context(0)
     ctx.set_option(ls.OPT_ZETA, w["zeta"])
+    ctx.set_option(ls.OPT_QR_PANEL, args.qr_panel)
     x = torch.empty(n, dtype=torch.float64, device="cuda")
     cases, speedups_stop, speedups_q = [], [], []
     kappas = [float(v) for v in args.kappas.split(",")] if args.kappas else list(w["kappas"])
@@ -297,6 +304,7 @@ def bench_large(args, w):
     ctx = ls.Context(0)
     ctx.set_option(ls.OPT_ZETA, w["zeta"])
     ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    ctx.set_option(ls.OPT_QR_PANEL, args.qr_panel)
     x = torch.empty(n, dtype=torch.float64, device="cuda")
     out = {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
@@ -494,6 +502,9 @@ def main():
     ap.add_argument("--betas", default="", help="mixed workload: ||r|| values to run (default: all three)")
     ap.add_argument("--modes", default="stop,q40",
                     help="mixed workload: stop (Section 3.3 rule, q <= 200) and/or q40 (fixed q)")
+    ap.add_argument("--qr-panel", type=int, default=0, choices=(0, 1),
+                    help="LS_OPT_QR_PANEL: 0 cooperative panels, 1 one launch per column (same bits)")
+    ap.add_argument("--verbose", action="store_true", help="a progress line on stderr after every solve")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -528,15 +539,24 @@ def main():
     ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
     ctx.set_option(ls.OPT_ZETA, w["zeta"])
 
-    for _ in range(args.warmup):
+    ctx.set_option(ls.OPT_QR_PANEL, args.qr_panel)
+
+    def progress(what):
+        if args.verbose:
+            print(f"[bench] {what} done at {time.perf_counter() - t_start:.1f}s", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    for k in range(args.warmup):
         ctx.solve(A, b, d, q, x)
+        progress(f"warm-up solve {k}")
     torch.cuda.synchronize()
     ctx.set_option(ls.OPT_PROFILE, 1)
     ctx.profile(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         ctx.solve(A, b, d, q, x)
+        progress(f"timed solve {k}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pass_ms, launches = ctx.profile(reset=True)

@@ -20,12 +20,16 @@
 //                   the same lists from the CSR, for the other shapes.
 //   k_gather_win    the same sums with each row of A fetched from HBM once or twice, not zeta times:
 //                   a work-group owns a 64-column slice of 16*rw sketch rows, accumulated in LDS;
-//                   the eight slices that share rows of A run on the eight XCDs at the same time
-//                   (one slice per XCD), and a work-group barrier every kWinPerStep windows keeps
+//                   when one XCD's compute units hold all sketch rows of a slice, the eight slices
+//                   that share rows of A run on the eight XCDs at the same time (one slice per
+//                   XCD), else each launch takes every row block of a few slices (row-major), so
+//                   A's columns are read once over all launches; a work-group barrier every kWinPerStep windows keeps
 //                   the 16 waves of a CU within a few thousand rows of A of each other, so the
 //                   other nonzeros of a row of A find it in that XCD's L2.  Each accumulator has one
 //                   owner (its wave) and receives its terms in ascending j, so the bits equal
 //                   k_gather's.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace {
@@ -707,16 +711,20 @@ k_wl_place_lds(int64_t m, int64_t d, int32_t zeta, int32_t nwl, int32_t nstep,
 // accumulator, so the order of each row's terms is the list's: ascending j).
 template <int RW, typename OT>
 __global__ void __launch_bounds__(kWinWaves * 64)
-k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0,
+k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0, int64_t nrb_all,
              const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
              const int32_t *__restrict__ woff, int32_t nstep, const uint32_t *__restrict__ lst,
              double scale, OT *__restrict__ B, int64_t ldb,
              OT *__restrict__ Sb, int64_t ldsb)
 {
     __shared__ double acc[kWinWaves * kWinMaxRows * 64];   // full size: one work-group per CU
-    const int slice = slice0 + (int)(blockIdx.x % 8);
+    // Slice-per-XCD launches (nrb_all == 0): work-group i takes slice slice0 + i % 8 (XCD i mod 8)
+    // and row block rb0 + i / 8.  Row-major launches (nrb_all > 0): work-group i takes row block
+    // i % nrb_all of slice slice0 + i / nrb_all, so one launch covers every sketch row of a few
+    // slices and A's columns are read once over all launches.
+    const int slice = nrb_all ? slice0 + (int)(blockIdx.x / nrb_all) : slice0 + (int)(blockIdx.x % 8);
     if (slice >= nslice) return;
-    const int64_t rb = rb0 + blockIdx.x / 8;
+    const int64_t rb = nrb_all ? (int64_t)(blockIdx.x % nrb_all) : rb0 + blockIdx.x / 8;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t ngroups = (d + RW - 1) / RW;
     const int64_t g = rb * kWinWaves + wave;
@@ -922,8 +930,34 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
 
 namespace {
 
-// One launch per (group of eight slices, share of the row blocks): every launch fills each XCD's
-// compute units with one work-group each, all starting together.
+template <typename OT>
+hipError_t gather_win_launch(hipStream_t s, dim3 grid, int64_t d, int64_t n, int32_t nslice,
+                             int32_t s0, int64_t rb0, int64_t nrb_all, const double *A, int64_t lda,
+                             const double *b, double scale, OT *B, int64_t ldb, OT *Sb, int64_t ldsb,
+                             const WinLists &w)
+{
+    switch (w.rw) {
+#define LS_WIN_CASE(R)                                                                                   \
+    case R:                                                                                              \
+        hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, s0,   \
+                           rb0, nrb_all, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb, Sb, ldsb);    \
+        break;
+    LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
+#undef LS_WIN_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+// Slice-per-XCD launches: each XCD takes its own slice of a group of eight, so a row of A is
+// fetched into each XCD's L2 once and shared there by the CUs that need it; a share of the row
+// blocks that one XCD's CUs hold goes in each launch, so a group of slices reads A's columns once
+// per share (four times at d = 4e4).  Beyond two shares the launches are row-major instead -- all
+// row blocks of as many slices as the device holds -- so A's columns are read once over all
+// launches, and the eight XCDs, which stream the same columns of the same rows at about the same
+// time, find each other's fetches in the memory-side cache.  (Measured at m = 1e6: d = 4e4,
+// n = 2000 took 14.8 ms against 16.0 ms in slice-per-XCD launches; d = 2e4, n = 1000, two shares,
+// took 8.0 ms against 6.4 ms, so it stays slice-per-XCD.)
 template <typename OT>
 hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                       const double *b, double scale, OT *B, int64_t ldb, OT *Sb, int64_t ldsb,
@@ -932,24 +966,24 @@ hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int6
     const int32_t nslice = (int32_t)((n + (b ? 1 : 0) + 63) / 64);
     const int64_t ngroups = (d + w.rw - 1) / w.rw;
     const int64_t nrb = (ngroups + kWinWaves - 1) / kWinWaves;
-    const int64_t launches = (nrb + w.cus - 1) / w.cus;
-    for (int32_t s0 = 0; s0 < nslice; s0 += 8) {
-        for (int64_t l = 0; l < launches; ++l) {
-            const int64_t rb0 = nrb * l / launches, rb1 = nrb * (l + 1) / launches;
-            const dim3 grid((unsigned)(8 * (rb1 - rb0)));
-            switch (w.rw) {
-#define LS_WIN_CASE(R)                                                                                   \
-            case R:                                                                                      \
-                hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, \
-                                   s0, rb0, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb,             \
-                                   Sb, ldsb);                                                            \
-                break;
-            LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
-#undef LS_WIN_CASE
-            default: return hipErrorInvalidValue;
+    const int64_t launches = (nrb + w.cus - 1) / w.cus;            // per group of eight slices
+    hipError_t e = hipSuccess;
+    if (nrb <= 2 * (int64_t)w.cus) {     // row-major measured slower with two shares per group
+        for (int32_t s0 = 0; s0 < nslice && e == hipSuccess; s0 += 8)
+            for (int64_t l = 0; l < launches && e == hipSuccess; ++l) {
+                const int64_t rb0 = nrb * l / launches, rb1 = nrb * (l + 1) / launches;
+                e = gather_win_launch(s, dim3((unsigned)(8 * (rb1 - rb0))), d, n, nslice, s0, rb0, 0, A, lda,
+                                      b, scale, B, ldb, Sb, ldsb, w);
             }
+    } else {
+        const int64_t per_launch = std::max<int64_t>(1, (int64_t)8 * w.cus / nrb);   // slices
+        for (int32_t s0 = 0; s0 < nslice && e == hipSuccess; s0 += (int32_t)per_launch) {
+            const int64_t ns = std::min<int64_t>(per_launch, nslice - s0);
+            e = gather_win_launch(s, dim3((unsigned)(ns * nrb)), d, n, nslice, s0, 0, nrb, A, lda, b, scale,
+                                  B, ldb, Sb, ldsb, w);
         }
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
