@@ -261,10 +261,6 @@ def bench_mixed(args, w):
                      if isinstance(v, dict)}
             print(f"[bench] kappa={kappa:.0e} r={beta:.0e}: {brief}", file=sys.stderr, flush=True)
             cases.append(row)
-            print(f"[bench] kappa={kappa:.0e} r={beta:.0e}: stop fp64 {row['stop_fp64']['ms']:.1f} ms "
-                  f"mixed {row['stop_mixed']['ms']:.1f} ms ({row['stop_mixed']['precision_used']}) "
-                  f"fe {row['stop_fp64']['forward_error']:.2e}/{row['stop_mixed']['forward_error']:.2e}",
-                  file=sys.stderr, flush=True)
             del p, A, b
             torch.cuda.empty_cache()
     def geomean(v):
