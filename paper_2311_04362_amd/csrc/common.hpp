@@ -13,6 +13,15 @@
 // Deferred device status bits, OR-ed into the context's status word by kernels.
 enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4, ST_TIMEOUT = 8 };
 
+// Look-ahead of the blocked QR: a second stream of the context and two events.  After each panel
+// the next panel's columns are updated on the caller's stream, which then factors that panel,
+// while the rest of the trailing matrix is updated on the side stream.
+struct QrAside {
+    hipStream_t side = nullptr;
+    hipEvent_t panel_done = nullptr;   // recorded on the caller's stream after each panel
+    hipEvent_t side_done = nullptr;    // recorded on the side stream after each trailing update
+};
+
 struct ls_ctx {
     int device = -1;                // -1: host-only context (argument checks only)
     // options
@@ -41,6 +50,7 @@ struct ls_ctx {
     int32_t *status = nullptr;      // device status word
     int32_t *status_host = nullptr; // pinned host copy
     void *scratch = nullptr;        // this device's copy of the fixed scratch (ls_gradient_noalloc)
+    QrAside qla;                    // QR look-ahead stream and events (null: no look-ahead)
     std::string err;
 };
 
@@ -160,11 +170,20 @@ struct QrBufsT {
     E *qtb;              // n
     E *RT;               // n x n  (R^T, row-major)
     unsigned *bar;       // grid-barrier counter of the cooperative panel kernel
+    // look-ahead only (null otherwise): the other panel's Householder vectors (panels alternate
+    // between V and V2) and the side stream's chunk partials and Z
+    E *V2 = nullptr;
+    E *Yp2 = nullptr;
+    E *Z2 = nullptr;
 };
 using QrBufs = QrBufsT<double>;
 using QrBufs32 = QrBufsT<float>;
-void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb);
-void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb);
+// The look-ahead pays when the trailing updates it overlaps with the panels are large: measured with
+// cooperative panels, 40.2 -> 35.4 ms at d = 4e4, n = 2000, but 4.20 -> 4.32 ms at d = 1e4, n = 500
+// and 10.80 -> 10.96 ms at d = 2e4, n = 1000 (stream and event costs per panel).
+inline bool qr_lookahead_pays(int64_t d, int64_t n) { return (double)d * (double)n >= 6e7; }
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb, bool lookahead = false);
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb, bool lookahead = false);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,
                               const double *Sb, const QrBufs &qb);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *B, int64_t ldb,
@@ -174,10 +193,12 @@ hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const float *
 hipError_t launch_round_sketch(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb64, const double *Sb,
                                const QrBufs32 &qb32);
 hipError_t launch_set_rhs(hipStream_t s, int64_t d, int64_t n, const double *Sb, const QrBufs &qb);
+// With la (and buffers from qr_bufs(.., lookahead = true)) the trailing updates are split between s
+// and la->side as QrAside describes; the factorization's bits are the same either way.
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
-                     bool per_column = false);
+                     bool per_column = false, const QrAside *la = nullptr);
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs32 &qb, int32_t *status,
-                     bool per_column = false);
+                     bool per_column = false, const QrAside *la = nullptr);
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,
                             int32_t *status);
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs32 &qb, float *R, int64_t ldr,

@@ -15,6 +15,11 @@
 // cores (v_mfma_f64_16x16x4f64, or v_mfma_f32_16x16x4f32 for the single-precision factorization of
 // the mixed-precision path); every reduction has a fixed order, so the factorization is
 // deterministic.  Every kernel is instantiated for FP64 and FP32.
+//
+// Look-ahead (large d n): after panel p the caller's stream updates only panel p+1's columns and
+// factors panel p+1, while a second stream of the context updates the other trailing columns, so
+// the latency-bound panel overlaps the bandwidth-bound update.  A column's update does not depend on
+// which other columns share its launch, so the factorization's bits do not change.
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -755,7 +760,7 @@ int64_t chunk_rows(int64_t rows)
 }  // namespace
 
 template <typename E>
-static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb)
+static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb, bool lookahead)
 {
     qb.ldw = ceil_div(n + 1, 8) * 8;
     qb.W = ar.take<E>((size_t)d * (size_t)qb.ldw);
@@ -770,10 +775,15 @@ static void qr_bufs_impl(Arena &ar, int64_t d, int64_t n, QrBufsT<E> &qb)
     qb.qtb = ar.take<E>((size_t)n);
     qb.RT = ar.take<E>((size_t)n * (size_t)n);
     qb.bar = ar.take<unsigned>(kBarFlags);
+    if (lookahead) {
+        qb.V2 = ar.take<E>((size_t)d * kNB);
+        qb.Yp2 = ar.take<E>((size_t)nch * kNB * (size_t)ldo);
+        qb.Z2 = ar.take<E>((size_t)kNB * (size_t)qb.ldw);
+    }
 }
 
-void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb) { qr_bufs_impl(ar, d, n, qb); }
-void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb) { qr_bufs_impl(ar, d, n, qb); }
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb, bool lookahead) { qr_bufs_impl(ar, d, n, qb, lookahead); }
+void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb, bool lookahead) { qr_bufs_impl(ar, d, n, qb, lookahead); }
 
 template <typename E>
 static hipError_t copy_sketch_impl(hipStream_t s, int64_t d, int64_t n, const E *B, int64_t ldb,
@@ -854,7 +864,7 @@ hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int 
 // One panel by the cooperative kernel if the device can hold its grid; returns false to request
 // the per-column path.
 template <typename E, int RB>
-bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb,
+bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBufsT<E> &qb, E *V,
                        bool &flags_zeroed, int32_t *status, hipError_t &err)
 {
     // One row per thread, as in k_panel_step: the work-groups' partial sums are then grouped exactly
@@ -864,7 +874,7 @@ bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBu
     err = hipSuccess;
     const int nwg = (int)ceil_div(rows, RB);
     if (nwg <= coop_capacity<E, 1, RB>() && nwg <= kBarFlags) {
-        err = launch_panel_coop<E, 1, RB>(s, d, p0, nbp, nwg, qb.W, qb.ldw, qb.V, qb.red, qb.tau, qb.bar,
+        err = launch_panel_coop<E, 1, RB>(s, d, p0, nbp, nwg, qb.W, qb.ldw, V, qb.red, qb.tau, qb.bar,
                                       !flags_zeroed, status);
         flags_zeroed = true;
         return true;
@@ -872,33 +882,70 @@ bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBu
     return false;
 }
 
+// Trailing update C <- Q_p^T C of columns [c0, c1) of the work matrix by panel p0's reflectors V
+// (the four launches described at the top), with chunk partials Yp and Z.  Each column's arithmetic
+// depends only on V, tau and that column, so splitting the columns over launches keeps the bits.
+template <typename E>
+void trailing_update(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, int64_t p0, int nbp,
+                     const E *V, E *Yp, E *Z, int64_t c0, int64_t c1)
+{
+    const int64_t ldw = qb.ldw;
+    const int64_t rows = d - p0;
+    const int64_t nc = c1 - c0;
+    const int64_t chunk = chunk_rows(rows);
+    const int nch = (int)ceil_div(rows, chunk);
+    const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
+    const E *C0 = qb.W + p0 * ldw + c0;
+    hipLaunchKernelGGL(k_vx_partial<E>, dim3(nch, (unsigned)ceil_div(kNB + nc, 64)), dim3(256), 0, s,
+                       rows, chunk, V, C0, ldw, (int64_t)kNB + nc, ldo, Yp);
+    hipLaunchKernelGGL(k_sum_partials<E>, dim3((unsigned)ceil_div(kNB + nc, 64), kNB / 4), dim3(256), 0, s,
+                       nch, ldo, (int64_t)kNB + nc, Yp);
+    hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, 1, ldo, Yp,
+                       qb.tau, p0, nbp, nc, Z, ldw);
+    hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
+                       dim3(256), 0, s, rows, nc, V, Z, ldw, qb.W + p0 * ldw + c0, ldw);
+}
+
+// The factorization, panel by panel.  With look-ahead (la and qb.V2), after panel p the caller's
+// stream s updates panel p+1's columns and factors panel p+1 while la->side updates the remaining
+// columns; s waits for the side stream before it touches columns the side stream updated, and panels
+// alternate between V and V2 so that panel p+1 never overwrites vectors the side stream still reads.
 template <typename E>
 hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, int32_t *status,
-                   bool per_column)
+                   bool per_column, const QrAside *la)
 {
     const int64_t ldw = qb.ldw;
     const int64_t red_stride = panel_wgs_max(d) * kNB + kNB;
     E *redA = qb.red, *redB = qb.red + red_stride;
+    const bool ahead = la && la->side && qb.V2 && !per_column && n > kNB;
     bool flags_zeroed = false;
+    if (ahead) {
+        // the side stream starts after everything before the factorization on s
+        if (hipEventRecord(la->panel_done, s) != hipSuccess ||
+            hipStreamWaitEvent(la->side, la->panel_done, 0) != hipSuccess ||
+            hipEventRecord(la->side_done, la->side) != hipSuccess)
+            return hipGetLastError();
+    }
     for (int64_t p0 = 0; p0 < n; p0 += kNB) {
         const int nbp = (int)((n - p0 < kNB) ? n - p0 : kNB);
         const int64_t rows = d - p0;
+        E *V = (ahead && ((p0 / kNB) & 1)) ? qb.V2 : qb.V;
         hipError_t err = hipSuccess;
         const int rb = panel_rows(d);
         const bool coop = !per_column && (rb == kRBLarge
-                                              ? panel_cooperative<E, kRBLarge>(s, d, p0, nbp, qb, flags_zeroed, status, err)
-                                              : panel_cooperative<E, kRBSmall>(s, d, p0, nbp, qb, flags_zeroed, status, err));
+                                              ? panel_cooperative<E, kRBLarge>(s, d, p0, nbp, qb, V, flags_zeroed, status, err)
+                                              : panel_cooperative<E, kRBSmall>(s, d, p0, nbp, qb, V, flags_zeroed, status, err));
         if (!coop) {
             const int nwg = (int)ceil_div(rows, rb);
             E *rin = redA, *rout = redB;
             for (int jc = -1; jc < nbp; ++jc) {
                 if (rb == kRBLarge)
                     hipLaunchKernelGGL((k_panel_step<E, kRBLarge>), dim3(nwg), dim3(kRBLarge), 0, s, d, p0, nbp, jc,
-                                       nwg, qb.W, ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                                       nwg, qb.W, ldw, V, rin, rin + (int64_t)nwg * kNB, rout,
                                        rout + (int64_t)nwg * kNB, qb.tau, status);
                 else
                     hipLaunchKernelGGL((k_panel_step<E, kRBSmall>), dim3(nwg), dim3(kRBSmall), 0, s, d, p0, nbp, jc,
-                                       nwg, qb.W, ldw, qb.V, rin, rin + (int64_t)nwg * kNB, rout,
+                                       nwg, qb.W, ldw, V, rin, rin + (int64_t)nwg * kNB, rout,
                                        rout + (int64_t)nwg * kNB, qb.tau, status);
                 E *t = rin;
                 rin = rout;
@@ -906,20 +953,22 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
             }
         }
         if (err != hipSuccess) return err;
-        const int64_t c_first = p0 + nbp;
-        const int64_t nc = n + 1 - c_first;            // trailing columns incl. S b (>= 1)
-        const int64_t chunk = chunk_rows(rows);
-        const int nch = (int)ceil_div(rows, chunk);
-        const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
-        const E *C0 = qb.W + p0 * ldw + c_first;
-        hipLaunchKernelGGL(k_vx_partial<E>, dim3(nch, (unsigned)ceil_div(kNB + nc, 64)), dim3(256), 0, s,
-                           rows, chunk, qb.V, C0, ldw, (int64_t)kNB + nc, ldo, qb.Yp);
-        hipLaunchKernelGGL(k_sum_partials<E>, dim3((unsigned)ceil_div(kNB + nc, 64), kNB / 4), dim3(256), 0, s,
-                           nch, ldo, (int64_t)kNB + nc, qb.Yp);
-        hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, 1, ldo, qb.Yp,
-                           qb.tau, p0, nbp, nc, qb.Z, ldw);
-        hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
-                           dim3(256), 0, s, rows, nc, qb.V, qb.Z, ldw, qb.W + p0 * ldw + c_first, ldw);
+        const int64_t c_first = p0 + nbp;                      // trailing columns c_first..n (S b last)
+        const int64_t next = (n - c_first < kNB) ? n - c_first : kNB;   // the next panel's columns
+        if (ahead && next > 0) {
+            // order: s records the panel, waits for the side stream's last update (it updated the
+            // next panel's columns), then updates them; the side stream waits for the panel only
+            if (hipEventRecord(la->panel_done, s) != hipSuccess ||
+                hipStreamWaitEvent(s, la->side_done, 0) != hipSuccess ||
+                hipStreamWaitEvent(la->side, la->panel_done, 0) != hipSuccess)
+                return hipGetLastError();
+            trailing_update(la->side, d, n, qb, p0, nbp, V, qb.Yp2, qb.Z2, c_first + next, n + 1);
+            if (hipEventRecord(la->side_done, la->side) != hipSuccess) return hipGetLastError();
+            trailing_update(s, d, n, qb, p0, nbp, V, qb.Yp, qb.Z, c_first, c_first + next);
+        } else {
+            if (ahead && hipStreamWaitEvent(s, la->side_done, 0) != hipSuccess) return hipGetLastError();
+            trailing_update(s, d, n, qb, p0, nbp, V, qb.Yp, qb.Z, c_first, n + 1);
+        }
     }
     return hipGetLastError();
 }
@@ -937,15 +986,15 @@ hipError_t extract_r_impl(hipStream_t s, int64_t n, const QrBufsT<E> &qb, E *R, 
 }  // namespace
 
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs &qb, int32_t *status,
-                     bool per_column)
+                     bool per_column, const QrAside *la)
 {
-    return qr_impl(s, d, n, qb, status, per_column);
+    return qr_impl(s, d, n, qb, status, per_column, la);
 }
 
 hipError_t launch_qr(hipStream_t s, int64_t d, int64_t n, const QrBufs32 &qb, int32_t *status,
-                     bool per_column)
+                     bool per_column, const QrAside *la)
 {
-    return qr_impl(s, d, n, qb, status, per_column);
+    return qr_impl(s, d, n, qb, status, per_column, la);
 }
 
 hipError_t launch_extract_r(hipStream_t s, int64_t n, const QrBufs &qb, double *R, int64_t ldr,

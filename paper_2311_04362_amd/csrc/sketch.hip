@@ -23,7 +23,8 @@
 //                   when one XCD's compute units hold all sketch rows of a slice, the eight slices
 //                   that share rows of A run on the eight XCDs at the same time (one slice per
 //                   XCD), else each launch takes every row block of a few slices (row-major), so
-//                   A's columns are read once over all launches; a work-group barrier every kWinPerStep windows keeps
+//                   A's columns are read once over all launches; a work-group barrier every
+//                   kWinPerStep windows (kWinRowMajorSync times that in row-major launches) keeps
 //                   the 16 waves of a CU within a few thousand rows of A of each other, so the
 //                   other nonzeros of a row of A find it in that XCD's L2.  Each accumulator has one
 //                   owner (its wave) and receives its terms in ascending j, so the bits equal
@@ -378,6 +379,11 @@ constexpr int kWinWaves = 16;          // waves per work-group (one group of rw 
 constexpr int kWinMaxRows = 20;        // rw at most: 16 x 20 x 64 doubles = 160 KiB of LDS
 constexpr int64_t kWinLen = 4096;      // rows of A per list window
 constexpr int kWinPerStep = 4;         // windows between two work-group barriers
+// Row-major launches (below) meet at a barrier every kWinRowMajorSync steps: an XCD there uses a row
+// of A about once, so the barriers only pace the CUs for the memory-side cache, and with about 65
+// entries per group and step at d = 4e4 each barrier waits on the group with the most.  Measured
+// at m = 4e6, n = 2000, d = 4e4: 59.1 ms every step, 57.9 ms every 4, 63.5 every 16, 69.8 never.
+constexpr int kWinRowMajorSync = 4;
 constexpr int kWinBatch = 8;           // rows of A in flight per wave (16 in flight fetch 1.8x the bytes)
 // A list entry packs the column j of S (bits 0..25), the entry's row within its group (26..30) and
 // the sign (31), so the column-sliced gather takes m < 2^26.
@@ -715,7 +721,7 @@ k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0, 
              const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
              const int32_t *__restrict__ woff, int32_t nstep, const uint32_t *__restrict__ lst,
              double scale, OT *__restrict__ B, int64_t ldb,
-             OT *__restrict__ Sb, int64_t ldsb)
+             OT *__restrict__ Sb, int64_t ldsb, int32_t sync_every)
 {
     __shared__ double acc[kWinWaves * kWinMaxRows * 64];   // full size: one work-group per CU
     // Slice-per-XCD launches (nrb_all == 0): work-group i takes slice slice0 + i % 8 (XCD i mod 8)
@@ -768,7 +774,7 @@ k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0, 
                 atomicAdd(my + r * 64, (v >> 31) ? -a : a);
             }
         }
-        __syncthreads();
+        if ((t + 1) % sync_every == 0) __syncthreads();
     }
     if (is_a || is_b) {
         OT *out = is_a ? B + col : Sb;
@@ -940,7 +946,8 @@ hipError_t gather_win_launch(hipStream_t s, dim3 grid, int64_t d, int64_t n, int
 #define LS_WIN_CASE(R)                                                                                   \
     case R:                                                                                              \
         hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, s0,   \
-                           rb0, nrb_all, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb, Sb, ldsb);    \
+                           rb0, nrb_all, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb, Sb, ldsb,     \
+                           nrb_all ? kWinRowMajorSync : 1);                                              \
         break;
     LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
 #undef LS_WIN_CASE

@@ -144,12 +144,16 @@ def test_qr_sketch_vs_oracle(ctx, d, n, kappa, panel):
         ctx.set_option(ls.OPT_QR_PANEL, 0)
 
 
-# d = 8192 is the first d whose panels take 512-row work-groups (256 below).
-@pytest.mark.parametrize("d", [3000, 8191, 8192, 12001])
-def test_qr_panel_paths_agree_bitwise(ctx, d):
-    """Both panel implementations do the same arithmetic in the same order."""
+# d = 8192 is the first d whose panels take 512-row work-groups (256 below).  d = 30000, n = 2010
+# (d n >= 6e7) takes the look-ahead on the cooperative path (trailing updates split between two
+# streams, panels alternating between two vector buffers; last panel 26 columns wide), against the
+# per-column path on one stream.
+@pytest.mark.parametrize("d,n", [(3000, 70), (8191, 70), (8192, 70), (12001, 70), (30000, 2010)])
+def test_qr_panel_paths_agree_bitwise(ctx, d, n):
+    """Both panel implementations, with or without the look-ahead, do the same arithmetic in the
+    same order."""
     rng = np.random.default_rng(3 + d)
-    B, Sb = dev(rng.standard_normal((d, 70))), dev(rng.standard_normal(d))
+    B, Sb = dev(rng.standard_normal((d, n))), dev(rng.standard_normal(d))
     R0, x0 = ctx.qr_sketch(B, Sb)
     ctx.set_option(ls.OPT_QR_PANEL, 1)
     R1, x1 = ctx.qr_sketch(B, Sb)
