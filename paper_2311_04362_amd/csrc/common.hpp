@@ -69,6 +69,9 @@ struct Arena {
 };
 
 // Sum of count values p[0], p[stride], ... added in ascending order, U loads in flight at a time.
+// The last count % U values are also loaded together before they are added (a loop of one load at
+// a time would put a memory round trip per value on the path: the panel reductions sum 2 to 5
+// values per thread).
 template <int U, typename T>
 __device__ __forceinline__ T strided_sum(const T *__restrict__ p, int count, int64_t stride)
 {
@@ -81,7 +84,14 @@ __device__ __forceinline__ T strided_sum(const T *__restrict__ p, int count, int
 #pragma unroll
         for (int u = 0; u < U; ++u) acc += v[u];
     }
-    for (; g < count; ++g) acc += p[(int64_t)g * stride];
+    if (g < count) {
+        T v[U - 1];
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u) v[u] = (g + u < count) ? p[(int64_t)(g + u) * stride] : T(0);
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u)
+            if (g + u < count) acc += v[u];
+    }
     return acc;
 }
 
@@ -98,7 +108,14 @@ __device__ __forceinline__ T strided_dot(const T *__restrict__ p, int64_t stride
 #pragma unroll
         for (int u = 0; u < U; ++u) acc += v[u] * w[i + u];
     }
-    for (; i < count; ++i) acc += p[(int64_t)i * stride] * w[i];
+    if (i < count) {
+        T v[U - 1];
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u) v[u] = (i + u < count) ? p[(int64_t)(i + u) * stride] : T(0);
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u)
+            if (i + u < count) acc += v[u] * w[i + u];
+    }
     return acc;
 }
 

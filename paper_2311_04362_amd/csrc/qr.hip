@@ -149,13 +149,14 @@ __device__ __forceinline__ int transpose_sum_index(int lane)
 //   red_in[w * kNB + l] = sum over rows of w (rows >= k) of W[i,k] W[i,p0+l]
 //   piv_in[l]           = W[k, p0+l] (the pivot row, before this step)
 // The launch writes the same quantities for column k+1 into red_out/piv_out.
-template <typename E, int RB>
+template <typename E, int RB, bool FULL>
 __global__ void __launch_bounds__(RB)
 k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W, int64_t ldw,
              E *__restrict__ V, const E *__restrict__ red_in,
              const E *__restrict__ piv_in, E *__restrict__ red_out,
              E *__restrict__ piv_out, E *__restrict__ tau, int32_t *__restrict__ status)
 {
+    const int nb = FULL ? kNB : nbp;          // panel width (kNB for every panel but the last)
     __shared__ E s_tl[kNB];
     __shared__ E s_f[kNB];
     __shared__ E s_red[RB / kNB][kNB];
@@ -168,7 +169,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 
     E w[kNB];
 #pragma unroll
-    for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nbp) ? W[i * ldw + p0 + l] : E(0);
+    for (int l = 0; l < kNB; ++l) w[l] = (row_ok && l < nb) ? W[i * ldw + p0 + l] : E(0);
 
     if (jc >= 0) {
         {   // reduce the partials: 8 contiguous groups of work-groups, then the groups in order
@@ -205,7 +206,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
             s_scal[1] = alpha - beta;
             if (blockIdx.x == 0) tau[k] = t;
             for (int l = 0; l < kNB; ++l)
-                s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * piv_in[l]) : E(0);
+                s_f[l] = (l > jc && l < nb) ? t * (s_tl[l] - beta * piv_in[l]) : E(0);
         }
         __syncthreads();
         if (row_ok) {
@@ -218,14 +219,14 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
                 const E vi = (i == k) ? s_scal[1] : wjc;
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
-                    if (l > jc && l < nbp) w[l] -= s_f[l] * vi;
+                    if (l > jc && l < nb) w[l] -= s_f[l] * vi;
                 vrow[jc] = vi;
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
                     if (l == jc) w[l] = (i == k) ? s_scal[0] : E(0);
 #pragma unroll
                 for (int l = 0; l < kNB; ++l)
-                    if (l >= jc && l < nbp) W[i * ldw + p0 + l] = w[l];
+                    if (l >= jc && l < nb) W[i * ldw + p0 + l] = w[l];
             } else {
                 vrow[jc] = E(0);
             }
@@ -238,7 +239,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
 
     // Partial sums for column k+1 over rows >= k+1, and its pivot row.
     const int jn = jc + 1;
-    if (jn < nbp) {
+    if (jn < nb) {
         const bool part = row_ok && i >= k + 1;
         E wn = E(0);
 #pragma unroll
@@ -247,7 +248,7 @@ k_panel_step(int64_t d, int64_t p0, int nbp, int jc, int nwg, E *__restrict__ W,
         const int wave = tid >> 6, lane = tid & 63;
         E pv[kNB];
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) pv[l] = (l >= jn && l < nbp) ? wn * w[l] : E(0);
+        for (int l = 0; l < kNB; ++l) pv[l] = (l >= jn && l < nb) ? wn * w[l] : E(0);
         const E tot = wave_transpose_sum(pv, lane);
         if ((lane & 1) == 0) s_part[wave][transpose_sum_index(lane)] = tot;
         if (i == k + 1) {
@@ -292,9 +293,18 @@ __device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned 
             __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
         for (;;) {
+            // a lane polls the flags of work-groups lane, lane + 64, ..., four loads in flight
             bool mine = true;
-            for (int g = threadIdx.x; g < nwg; g += 64)
-                mine &= __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+            for (int g0 = threadIdx.x; g0 < nwg; g0 += 256) {
+                unsigned f[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    f[u] = (g0 + 64 * u < nwg)
+                               ? __hip_atomic_load(flags + g0 + 64 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : epoch;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) mine &= f[u] >= epoch;
+            }
             if (__all(mine)) break;
             if (++spins > kSpinLimit) {
                 if (threadIdx.x == 0) atomicOr(status, ST_TIMEOUT);
@@ -307,12 +317,13 @@ __device__ __forceinline__ void flag_barrier(unsigned *flags, int nwg, unsigned 
     __syncthreads();
 }
 
-template <typename E, int RPT, int RB>
+template <typename E, int RPT, int RB, bool FULL>
 __global__ void __launch_bounds__(RB)
 k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t ldw,
              E *__restrict__ V, E *__restrict__ red, E *__restrict__ tau,
              unsigned *__restrict__ bar, unsigned epoch0, int32_t *__restrict__ status)
 {
+    const int nb = FULL ? kNB : nbp;          // panel width (kNB for every panel but the last)
     __shared__ E s_tl[kNB];
     __shared__ E s_f[kNB];
     __shared__ E s_part[RB / 64][kNB];
@@ -335,14 +346,14 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
         row[r] = p0 + ((int64_t)blockIdx.x * RPT + r) * RB + tid;
         ok[r] = row[r] < d;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) w[r][l] = (ok[r] && l < nbp) ? W[row[r] * ldw + p0 + l] : E(0);
+        for (int l = 0; l < kNB; ++l) w[r][l] = (ok[r] && l < nb) ? W[row[r] * ldw + p0 + l] : E(0);
     }
     // One column step.  The steps are expanded at compile time (for_each_column below, always
     // inlined), so every register index is static -- a runtime index would put the row arrays in
     // scratch memory or behind select chains.
     auto column = [&](auto jcc) __attribute__((always_inline)) {
         constexpr int jc = decltype(jcc)::value;
-        if (jc >= nbp) return;
+        if (jc >= nb) return;
         const int64_t k = p0 + jc;
         const int pb = jc & 1;
         E *rb = red + (int64_t)pb * nwg * kNB;
@@ -356,7 +367,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
                 const bool use = ok[r] && row[r] >= k;
 #pragma unroll
                 for (int l = jc; l < kNB; ++l)
-                    if (use && l < nbp) pv[l] += w[r][jc] * w[r][l];
+                    if (use && l < nb) pv[l] += w[r][jc] * w[r][l];
             }
             const E tot = wave_transpose_sum(pv, lane);
             if ((lane & 1) == 0) s_part[wave][tidx] = tot;
@@ -413,7 +424,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
                 t = E(1) / (sigma * (sigma + fabs(alpha)));   // 2 / (v^T v)
             }
             const int l = tid;
-            s_f[l] = (l > jc && l < nbp) ? t * (s_tl[l] - beta * s_piv[l]) : E(0);
+            s_f[l] = (l > jc && l < nb) ? t * (s_tl[l] - beta * s_piv[l]) : E(0);
             if (tid == 0) {
                 if (sigma == E(0)) atomicOr(status, ST_RANK);
                 if (!isfinite(sigma) || !isfinite(alpha)) atomicOr(status, ST_NONFINITE);
@@ -434,7 +445,7 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
             if (!below) continue;
 #pragma unroll
             for (int l = jc + 1; l < kNB; ++l)
-                if (l < nbp) w[r][l] -= s_f[l] * vi;
+                if (l < nb) w[r][l] -= s_f[l] * vi;
             w[r][jc] = (row[r] == k) ? s_scal[0] : E(0);
         }
     };
@@ -444,10 +455,10 @@ k_panel_coop(int64_t d, int64_t p0, int nbp, int nwg, E *__restrict__ W, int64_t
         if (!ok[r]) continue;
 #pragma unroll
         for (int l = 0; l < kNB; ++l)
-            if (l < nbp) W[row[r] * ldw + p0 + l] = w[r][l];
+            if (l < nb) W[row[r] * ldw + p0 + l] = w[r][l];
         E *vrow = V + (row[r] - p0) * kNB;
 #pragma unroll
-        for (int l = 0; l < kNB; ++l) vrow[l] = (l < nbp) ? s_v[l][r * RB + tid] : E(0);
+        for (int l = 0; l < kNB; ++l) vrow[l] = (l < nb) ? s_v[l][r * RB + tid] : E(0);
     }
 }
 
@@ -826,7 +837,7 @@ namespace {
 
 // Work-groups of k_panel_coop<E, RPT> that can be co-resident on the current device (0: cooperative
 // launch unavailable).  Cached per device.
-template <typename E, int RPT, int RB>
+template <typename E, int RPT, int RB, bool FULL>
 int coop_capacity()
 {
     static int cache[64];
@@ -836,7 +847,7 @@ int coop_capacity()
     int coop = 0, cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB>), RB, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB, FULL>), RB, 0) != hipSuccess ||
         per_cu <= 0) {
         (void)hipGetLastError();
         cache[dev] = -1;
@@ -849,7 +860,7 @@ int coop_capacity()
 // The step flags carry epochs that grow over all panels of one factorization (panel p uses
 // p (kNB + 1) + 1 ... p (kNB + 1) + kNB), so they are cleared once, before its first cooperative
 // panel (zero_flags), not before every panel.
-template <typename E, int RPT, int RB>
+template <typename E, int RPT, int RB, bool FULL>
 hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int nwg, E *W,
                              int64_t ldw, E *V, E *red, E *tau, unsigned *bar, bool zero_flags,
                              int32_t *status)
@@ -857,7 +868,7 @@ hipError_t launch_panel_coop(hipStream_t s, int64_t d, int64_t p0, int nbp, int 
     if (zero_flags) hipLaunchKernelGGL(k_zero_u32, dim3(kBarFlags / 256), dim3(256), 0, s, bar, kBarFlags);
     unsigned epoch0 = (unsigned)(p0 / kNB) * (unsigned)(kNB + 1);
     void *args[] = {&d, &p0, &nbp, &nwg, &W, &ldw, &V, &red, &tau, &bar, &epoch0, &status};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB>), dim3(nwg),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_panel_coop<E, RPT, RB, FULL>), dim3(nwg),
                                       dim3(RB), args, 0, s);
 }
 
@@ -873,13 +884,15 @@ bool panel_cooperative(hipStream_t s, int64_t d, int64_t p0, int nbp, const QrBu
     const int64_t rows = d - p0;
     err = hipSuccess;
     const int nwg = (int)ceil_div(rows, RB);
-    if (nwg <= coop_capacity<E, 1, RB>() && nwg <= kBarFlags) {
-        err = launch_panel_coop<E, 1, RB>(s, d, p0, nbp, nwg, qb.W, qb.ldw, V, qb.red, qb.tau, qb.bar,
-                                      !flags_zeroed, status);
-        flags_zeroed = true;
-        return true;
-    }
-    return false;
+    const bool full = nbp == kNB;
+    if (nwg > kBarFlags || nwg > (full ? coop_capacity<E, 1, RB, true>() : coop_capacity<E, 1, RB, false>()))
+        return false;
+    err = full ? launch_panel_coop<E, 1, RB, true>(s, d, p0, nbp, nwg, qb.W, qb.ldw, V, qb.red, qb.tau, qb.bar,
+                                                   !flags_zeroed, status)
+               : launch_panel_coop<E, 1, RB, false>(s, d, p0, nbp, nwg, qb.W, qb.ldw, V, qb.red, qb.tau, qb.bar,
+                                                    !flags_zeroed, status);
+    flags_zeroed = true;
+    return true;
 }
 
 // Trailing update C <- Q_p^T C of columns [c0, c1) of the work matrix by panel p0's reflectors V
@@ -938,15 +951,19 @@ hipError_t qr_impl(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, in
         if (!coop) {
             const int nwg = (int)ceil_div(rows, rb);
             E *rin = redA, *rout = redB;
+            const bool full = nbp == kNB;
             for (int jc = -1; jc < nbp; ++jc) {
-                if (rb == kRBLarge)
-                    hipLaunchKernelGGL((k_panel_step<E, kRBLarge>), dim3(nwg), dim3(kRBLarge), 0, s, d, p0, nbp, jc,
-                                       nwg, qb.W, ldw, V, rin, rin + (int64_t)nwg * kNB, rout,
-                                       rout + (int64_t)nwg * kNB, qb.tau, status);
-                else
-                    hipLaunchKernelGGL((k_panel_step<E, kRBSmall>), dim3(nwg), dim3(kRBSmall), 0, s, d, p0, nbp, jc,
-                                       nwg, qb.W, ldw, V, rin, rin + (int64_t)nwg * kNB, rout,
-                                       rout + (int64_t)nwg * kNB, qb.tau, status);
+#define LS_PANEL_STEP(RBV, FULLV)                                                                              \
+    hipLaunchKernelGGL((k_panel_step<E, RBV, FULLV>), dim3(nwg), dim3(RBV), 0, s, d, p0, nbp, jc, nwg, qb.W, ldw, V, \
+                       rin, rin + (int64_t)nwg * kNB, rout, rout + (int64_t)nwg * kNB, qb.tau, status)
+                if (rb == kRBLarge) {
+                    if (full) LS_PANEL_STEP(kRBLarge, true);
+                    else LS_PANEL_STEP(kRBLarge, false);
+                } else {
+                    if (full) LS_PANEL_STEP(kRBSmall, true);
+                    else LS_PANEL_STEP(kRBSmall, false);
+                }
+#undef LS_PANEL_STEP
                 E *t = rin;
                 rin = rout;
                 rout = t;
