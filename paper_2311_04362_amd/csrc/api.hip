@@ -120,7 +120,8 @@ ls_status pass_events(ls_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1)
     if (!ctx->profile) return LS_OK;
     while (ctx->ev_pool.size() < ctx->ev_used + 2) {
         hipEvent_t e;
-        HIP_TRY(ctx, hipEventCreate(&e), "create event");
+        // timestamps only: no system-scope fence at each record (about 5.6 us per record with it)
+        HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "create event");
         ctx->ev_pool.push_back(e);
     }
     e0 = ctx->ev_pool[ctx->ev_used];
