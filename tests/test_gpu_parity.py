@@ -144,7 +144,7 @@ def test_qr_sketch_vs_oracle(ctx, d, n, kappa, panel):
         ctx.set_option(ls.OPT_QR_PANEL, 0)
 
 
-# d = 8192 is the first d whose panels take 512-row work-groups (256 below).  d = 30000, n = 2010
+# d = 8192 is the first d whose panels take 512-row work-groups (128 below).  d = 30000, n = 2010
 # (d n >= 6e7) takes the look-ahead on the cooperative path (trailing updates split between two
 # streams, panels alternating between two vector buffers; last panel 26 columns wide), against the
 # per-column path on one stream.
