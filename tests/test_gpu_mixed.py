@@ -98,10 +98,12 @@ def test_qr_f32_vs_oracle(ctx, d, n, kappa, panel):
     assert np.linalg.norm(xo - x64) <= tol + 1e-30
 
 
-def test_qr_f32_panel_paths_agree_bitwise(ctx):
-    rng = np.random.default_rng(8)
-    B = dev(rng.standard_normal((3000, 70)).astype(np.float32))
-    Sb = dev(rng.standard_normal(3000).astype(np.float32))
+# (30000, 2010): d n >= 6e7, so the cooperative path takes the look-ahead (two streams) in FP32 too.
+@pytest.mark.parametrize("d,n", [(3000, 70), (30000, 2010)])
+def test_qr_f32_panel_paths_agree_bitwise(ctx, d, n):
+    rng = np.random.default_rng(8 + n)
+    B = dev(rng.standard_normal((d, n)).astype(np.float32))
+    Sb = dev(rng.standard_normal(d).astype(np.float32))
     R0, x0 = ctx.qr_sketch_f32(B, Sb)
     ctx.set_option(ls.OPT_QR_PANEL, 1)
     R1, x1 = ctx.qr_sketch_f32(B, Sb)
