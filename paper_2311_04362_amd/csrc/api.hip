@@ -274,11 +274,24 @@ static void release_aside(QrAside &la)
     la = QrAside{};
 }
 
-// The context's QR look-ahead for a d x n factorization, or null: none without the side stream, on
-// the per-column panel path, or where it does not pay.
-static const QrAside *qr_aside(const ls_ctx *ctx, int64_t d, int64_t n)
+// The context's QR look-ahead for a d x n factorization, or null: on the per-column panel path,
+// where it does not pay, or if its stream cannot be made.  The side stream (default priority) and
+// its two events are created on the first factorization that uses them, so contexts that never
+// factor a large sketch hold no second stream (a process has few hardware queues to share).
+static const QrAside *qr_aside(ls_ctx *ctx, int64_t d, int64_t n)
 {
-    return (ctx->qla.side && ctx->qr_panel != 1 && qr_lookahead_pays(d, n)) ? &ctx->qla : nullptr;
+    if (ctx->qr_panel == 1 || !qr_lookahead_pays(d, n) || ctx->device < 0) return nullptr;
+    if (!ctx->qla.side) {
+        DeviceGuard g(ctx->device);
+        if (!g.ok || hipStreamCreateWithFlags(&ctx->qla.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->qla.panel_done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->qla.side_done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            release_aside(ctx->qla);
+            return nullptr;
+        }
+    }
+    return &ctx->qla;
 }
 
 // Algorithm 2 in FP64 (the body of ls_solve).
@@ -290,9 +303,10 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
     QrBufs qb{};
     IterBufs ib{};
     double *R = nullptr, *est_work = nullptr;
+    const QrAside *la = qr_aside(ctx, d, n);   // decided once: sizing and carve agree
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
         sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather);
-        qr_bufs(ar, d, n, qb, qr_aside(ctx, d, n) != nullptr);
+        qr_bufs(ar, d, n, qb, la != nullptr);
         iter_bufs(ar, m, n, ib, false);
         R = ar.take<double>((size_t)n * (size_t)n);
         est_work = ar.take<double>((size_t)3 * (size_t)n);
@@ -307,7 +321,7 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
     // (b) QR of [B | S b], R and Q^T S b, x0 = R^{-1} (Q^T S b)[0:n].
     {
         Range r("ls_solve: QR and x0");
-        HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, qr_aside(ctx, d, n)), "QR kernels");
+        HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
         HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
         HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
     }
@@ -345,10 +359,11 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     IterBufs ib{}, ibs{};
     float *R = nullptr, *est_work = nullptr;
     double *Sb = nullptr, *R64 = nullptr, *est64 = nullptr;
+    const QrAside *la = qr_aside(ctx, d, n);   // decided once: sizing and carve agree
     LS_TRY(with_arena(ctx, [&](Arena &ar) {
         sketch_bufs(ar, m, d, zeta, sb, n, ctx->gather);
-        qr_bufs(ar, d, n, qb64, qr_aside(ctx, d, n) != nullptr);
-        qr_bufs(ar, d, n, qb, qr_aside(ctx, d, n) != nullptr);
+        qr_bufs(ar, d, n, qb64, la != nullptr);
+        qr_bufs(ar, d, n, qb, la != nullptr);
         iter_bufs(ar, m, n, ib, false);
         iter_bufs(ar, d, n, ibs, false);
         R = ar.take<float>((size_t)n * (size_t)n);
@@ -364,7 +379,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     HIP_TRY(ctx, launch_gather(s, d, n, A, lda, b, sb.rowptr, sb.cols, scale, qb64.W, qb64.ldw, Sb, 1, &sb.win), "gather kernel");
     HIP_TRY(ctx, launch_round_sketch(s, d, n, qb64, Sb, qb), "round sketch");
     // (b) FP32 QR, R, the FP32 start, FP32 estimators; the fallback decision on the host.
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, qr_aside(ctx, d, n)), "QR kernels");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
     HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
@@ -381,7 +396,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
         ctx->last_steps = q;
         HIP_TRY(ctx, hipMemsetAsync(ctx->status, 0, sizeof(int32_t), s), "clear status");
         HIP_TRY(ctx, launch_set_rhs(s, d, n, Sb, qb64), "set rhs");
-        HIP_TRY(ctx, launch_qr(s, d, n, qb64, ctx->status, ctx->qr_panel == 1, qr_aside(ctx, d, n)), "QR kernels");
+        HIP_TRY(ctx, launch_qr(s, d, n, qb64, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
         HIP_TRY(ctx, launch_extract_r(s, n, qb64, R64, n, ctx->status), "extract R");
         HIP_TRY(ctx, launch_back_substitution(s, n, R64, n, qb64.RT, qb64.qtb, x, ctx->status), "x0 solve");
         return iterate_fp64(ctx, s, m, n, A, lda, b, d, q, x, R64, qb64.RT, ib, est64);
@@ -465,14 +480,6 @@ ls_status ls_create(int device, ls_ctx **out)
         (void)hipHostFree(ctx->status_host);
         delete ctx;
         return LS_ERR_DEVICE;
-    }
-    // QR look-ahead: a side stream (default priority) and two events; without them the QR runs on
-    // the caller's stream alone.
-    if ((hipStreamCreateWithFlags(&ctx->qla.side, hipStreamNonBlocking) != hipSuccess ||
-         hipEventCreateWithFlags(&ctx->qla.panel_done, hipEventDisableTiming) != hipSuccess ||
-         hipEventCreateWithFlags(&ctx->qla.side_done, hipEventDisableTiming) != hipSuccess)) {
-        (void)hipGetLastError();
-        release_aside(ctx->qla);
     }
     *out = ctx;
     return LS_OK;
@@ -652,9 +659,10 @@ ls_status ls_qr_sketch(ls_ctx *ctx, void *stream, int64_t d, int64_t n, const do
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     QrBufs qb{};
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb, qr_aside(ctx, d, n) != nullptr); }));
+    const QrAside *la = qr_aside(ctx, d, n);   // decided once: sizing and carve agree
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb, la != nullptr); }));
     HIP_TRY(ctx, launch_copy_sketch(s, d, n, B, ldb, Sb, qb), "copy sketch");
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, qr_aside(ctx, d, n)), "QR kernels");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, ldr, ctx->status), "extract R");
     if (x0) HIP_TRY(ctx, launch_back_substitution(s, n, R, ldr, qb.RT, qb.qtb, x0, ctx->status), "x0 solve");
     return LS_OK;
@@ -775,9 +783,10 @@ ls_status ls_qr_sketch_f32(ls_ctx *ctx, void *stream, int64_t d, int64_t n, cons
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     QrBufs32 qb{};
-    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb, qr_aside(ctx, d, n) != nullptr); }));
+    const QrAside *la = qr_aside(ctx, d, n);   // decided once: sizing and carve agree
+    LS_TRY(with_arena(ctx, [&](Arena &ar) { qr_bufs(ar, d, n, qb, la != nullptr); }));
     HIP_TRY(ctx, launch_copy_sketch(s, d, n, B, ldb, Sb, qb), "copy sketch");
-    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, qr_aside(ctx, d, n)), "QR kernels");
+    HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, ldr, ctx->status), "extract R");
     if (x0) HIP_TRY(ctx, launch_back_substitution(s, n, (const float *)R, ldr, qb.RT, qb.qtb, x0, ctx->status), "x0 solve");
     return LS_OK;
