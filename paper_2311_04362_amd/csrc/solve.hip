@@ -5,9 +5,9 @@
 //   k_solve       one work-group: R^T y = c by forward substitution, R d = y by back substitution
 //                 (32-wide diagonal blocks by one wave while the other waves apply earlier blocks
 //                 as coalesced GEMV updates; no inverse matrix is ever formed), then the update.
-//                 One CU streams R twice, so the GEMV waves read two doubles per 16-byte load
-//                 when the rows allow it (FP64, even n and ldr): one CU's read rate rises from
-//                 about 76 to 114 GB/s, and each unknown's sum keeps its order and its bits.
+//                 One CU streams R twice, so the GEMV waves read 16 bytes per load (two doubles,
+//                 or four floats) when the rows allow it: one CU's read rate rises from about 76
+//                 to 114 GB/s, and each unknown's sum keeps its order and its bits.
 //   k_back        back substitution alone (x_0).
 //   k_transpose   R^T for the column reads of the back substitution.
 //
@@ -70,18 +70,23 @@ __device__ __forceinline__ T rows_dot(__amdgpu_buffer_rsrc_t rs, int64_t ld, int
     return acc;
 }
 
-// VW consecutive entries of one row (VW = 1: rows_load; VW = 2: one 16-byte load of two doubles,
-// the byte offsets 16-byte aligned).
+// VW consecutive entries of one row (VW = 1: rows_load; otherwise one 16-byte load of two doubles
+// or four floats, the byte offsets 16-byte aligned).
 template <typename T, int VW>
 __device__ __forceinline__ void rows_loadw(__amdgpu_buffer_rsrc_t rs, uint32_t vbytes, uint32_t sbytes, T (&out)[VW])
 {
     if constexpr (VW == 1) {
         out[0] = rows_load(rs, (T *)nullptr, vbytes, sbytes);
     } else {
-        static_assert(VW == 2 && sizeof(T) == 8, "16-byte loads take two doubles");
+        static_assert(VW * sizeof(T) == 16, "16-byte loads take two doubles or four floats");
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vbytes, (int)sbytes, 0);
-        out[0] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[1] << 32) | (uint32_t)q[0]);
-        out[1] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[3] << 32) | (uint32_t)q[2]);
+        if constexpr (sizeof(T) == 8) {
+            out[0] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[1] << 32) | (uint32_t)q[0]);
+            out[1] = __builtin_bit_cast(double, ((uint64_t)(uint32_t)q[3] << 32) | (uint32_t)q[2]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = __builtin_bit_cast(float, (uint32_t)q[v]);
+        }
     }
 }
 
@@ -849,12 +854,17 @@ hipError_t transpose_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, T *
     return hipGetLastError();
 }
 
-// The GEMV waves read two doubles per 16-byte load when every row of R and R^T starts 16-byte
-// aligned (FP64 factors, n and ldr even, aligned bases); the sums are the same either way.
+// The GEMV waves read 16 bytes per load (two doubles or four floats) when every row of R and R^T
+// starts 16-byte aligned (n and ldr multiples of 16 / sizeof(T), aligned bases); the sums are the
+// same either way.  FP32 factors take it above n = 512 only: ls_precond_solve_f32 measured 340 ->
+// 286 us at n = 2000 and 114 -> 106 us at n = 1000, but 47.3 -> 50.8 us at n = 500 (FP64: faster
+// at every n measured, 500 to 2000).
 template <typename T>
 bool wide_rows(int64_t n, const T *R, int64_t ldr, const T *RT)
 {
-    return sizeof(T) == 8 && n % 2 == 0 && ldr % 2 == 0 && (uintptr_t)R % 16 == 0 && (uintptr_t)RT % 16 == 0;
+    constexpr int64_t k = 16 / sizeof(T);
+    return (sizeof(T) == 8 || n > 512) && n % k == 0 && ldr % k == 0 && (uintptr_t)R % 16 == 0 &&
+           (uintptr_t)RT % 16 == 0;
 }
 
 template <typename T>
@@ -864,7 +874,7 @@ hipError_t solve_update_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, 
 {
     const size_t lds = (size_t)padded<kSolveBlock>(n) * sizeof(T);
     if (wide_rows(n, R, ldr, RT))
-        hipLaunchKernelGGL((k_solve<T, kSolveBlock, sizeof(T) == 8 ? 2 : 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
+        hipLaunchKernelGGL((k_solve<T, kSolveBlock, 16 / sizeof(T)>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
                            ldr, RT, c, x, xprev, dout, mode, alpha, beta, status, st.state, st.scal, st.dx,
                            st.gamma, st.rho, st.check, st.grow);
     else
@@ -889,7 +899,7 @@ hipError_t back_impl(hipStream_t s, int64_t n, const T *R, int64_t ldr, const T 
 {
     const size_t lds = (size_t)padded<kSolveBlock>(n) * sizeof(T);
     if (wide_rows(n, R, ldr, RT))
-        hipLaunchKernelGGL((k_back<T, kSolveBlock, sizeof(T) == 8 ? 2 : 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
+        hipLaunchKernelGGL((k_back<T, kSolveBlock, 16 / sizeof(T)>), dim3(1), dim3(kSolveThreads), lds, s, n, R,
                            ldr, RT, y, x, status);
     else
         hipLaunchKernelGGL((k_back<T, kSolveBlock, 1>), dim3(1), dim3(kSolveThreads), lds, s, n, R, ldr, RT, y, x,
