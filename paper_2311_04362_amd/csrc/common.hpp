@@ -133,6 +133,7 @@ struct WinLists {
     int32_t nwl = 0;       // windows: ceil(m / kWinLen)
     int32_t nstep = 0;     // barrier steps: ceil(nwl / kWinPerStep)
     int32_t cus = 0;       // work-groups per XCD and launch (compute units per XCD)
+    int32_t zeta = 0;      // nonzeros per column of S (list entries per row of A)
     uint32_t *lst = nullptr;   // m*zeta entries (j | row in group << 26 | sign << 31), group lists back to back
     int32_t *ctab = nullptr;   // (nwl+1) x d: entries of row k in windows < w
     int32_t *stab = nullptr;   // nwl x d: list offsets (k_win_scan)

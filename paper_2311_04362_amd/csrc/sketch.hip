@@ -379,10 +379,11 @@ constexpr int kWinWaves = 16;          // waves per work-group (one group of rw 
 constexpr int kWinMaxRows = 20;        // rw at most: 16 x 20 x 64 doubles = 160 KiB of LDS
 constexpr int64_t kWinLen = 4096;      // rows of A per list window
 constexpr int kWinPerStep = 4;         // windows between two work-group barriers
-// Row-major launches (below) meet at a barrier every kWinRowMajorSync steps: an XCD there uses a row
-// of A about once, so the barriers only pace the CUs for the memory-side cache, and with about 65
-// entries per group and step at d = 4e4 each barrier waits on the group with the most.  Measured
-// at m = 4e6, n = 2000, d = 4e4: 59.1 ms every step, 57.9 ms every 4, 63.5 every 16, 69.8 never.
+// Row-major launches (below) with fewer than 128 list entries per group and step (d above about
+// 2.5e4) meet at a barrier only every kWinRowMajorSync steps: each barrier waits on the group with
+// the most entries, which weighs more the fewer there are.  Measured at m = 4e6, n = 2000,
+// d = 4e4 (row blocks over all XCDs): 59.1 ms every step, 57.9 every 4, 63.5 every 16, 69.8 never;
+// with each slice on its own XCDs: 50.9 every step, 49.5 every 2, 48.6 every 4.
 constexpr int kWinRowMajorSync = 4;
 constexpr int kWinBatch = 8;           // rows of A in flight per wave (16 in flight fetch 1.8x the bytes)
 // A list entry packs the column j of S (bits 0..25), the entry's row within its group (26..30) and
@@ -721,16 +722,31 @@ k_gather_win(int64_t d, int64_t n, int32_t nslice, int32_t slice0, int64_t rb0, 
              const double *__restrict__ A, int64_t lda, const double *__restrict__ b,
              const int32_t *__restrict__ woff, int32_t nstep, const uint32_t *__restrict__ lst,
              double scale, OT *__restrict__ B, int64_t ldb,
-             OT *__restrict__ Sb, int64_t ldsb, int32_t sync_every)
+             OT *__restrict__ Sb, int64_t ldsb, int32_t sync_every, int32_t xgroups)
 {
     __shared__ double acc[kWinWaves * kWinMaxRows * 64];   // full size: one work-group per CU
     // Slice-per-XCD launches (nrb_all == 0): work-group i takes slice slice0 + i % 8 (XCD i mod 8)
     // and row block rb0 + i / 8.  Row-major launches (nrb_all > 0): work-group i takes row block
     // i % nrb_all of slice slice0 + i / nrb_all, so one launch covers every sketch row of a few
-    // slices and A's columns are read once over all launches.
-    const int slice = nrb_all ? slice0 + (int)(blockIdx.x / nrb_all) : slice0 + (int)(blockIdx.x % 8);
+    // slices and A's columns are read once over all launches.  With xgroups > 0 (a divisor of 8,
+    // the launch's slices) the row-major launch keeps each slice on its own XCDs: slice j of the
+    // launch on the XCDs x with x % xgroups == j, its row blocks dealt over them, so the nonzeros
+    // of a row of A meet in fewer L2s.
+    int slice;
+    int64_t rb;
+    if (nrb_all == 0) {
+        slice = slice0 + (int)(blockIdx.x % 8);
+        rb = rb0 + blockIdx.x / 8;
+    } else if (xgroups > 0) {
+        const int x = (int)(blockIdx.x % 8);
+        slice = slice0 + x % xgroups;
+        rb = (int64_t)(blockIdx.x / 8) * (8 / xgroups) + x / xgroups;
+        if (rb >= nrb_all) return;
+    } else {
+        slice = slice0 + (int)(blockIdx.x / nrb_all);
+        rb = (int64_t)(blockIdx.x % nrb_all);
+    }
     if (slice >= nslice) return;
-    const int64_t rb = nrb_all ? (int64_t)(blockIdx.x % nrb_all) : rb0 + blockIdx.x / 8;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t ngroups = (d + RW - 1) / RW;
     const int64_t g = rb * kWinWaves + wave;
@@ -823,6 +839,7 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
         w.active = true;
         w.cus = cus;
         w.rw = win_rows(d, cus);
+        w.zeta = zeta;
         w.nwl = (int32_t)((m + kWinLen - 1) / kWinLen);
         w.nstep = (w.nwl + kWinPerStep - 1) / kWinPerStep;
         const int64_t ngroups = (d + w.rw - 1) / w.rw;
@@ -940,14 +957,14 @@ template <typename OT>
 hipError_t gather_win_launch(hipStream_t s, dim3 grid, int64_t d, int64_t n, int32_t nslice,
                              int32_t s0, int64_t rb0, int64_t nrb_all, const double *A, int64_t lda,
                              const double *b, double scale, OT *B, int64_t ldb, OT *Sb, int64_t ldsb,
-                             const WinLists &w)
+                             const WinLists &w, int32_t xgroups = 0, int32_t sync_every = 1)
 {
     switch (w.rw) {
 #define LS_WIN_CASE(R)                                                                                   \
     case R:                                                                                              \
         hipLaunchKernelGGL((k_gather_win<R, OT>), grid, dim3(kWinWaves * 64), 0, s, d, n, nslice, s0,   \
                            rb0, nrb_all, A, lda, b, w.woff, w.nstep, w.lst, scale, B, ldb, Sb, ldsb,     \
-                           nrb_all ? kWinRowMajorSync : 1);                                              \
+                           sync_every, xgroups);                                                         \
         break;
     LS_WIN_CASE(4) LS_WIN_CASE(8) LS_WIN_CASE(12) LS_WIN_CASE(16) LS_WIN_CASE(20)
 #undef LS_WIN_CASE
@@ -956,15 +973,18 @@ hipError_t gather_win_launch(hipStream_t s, dim3 grid, int64_t d, int64_t n, int
     return hipSuccess;
 }
 
-// Slice-per-XCD launches: each XCD takes its own slice of a group of eight, so a row of A is
-// fetched into each XCD's L2 once and shared there by the CUs that need it; a share of the row
-// blocks that one XCD's CUs hold goes in each launch, so a group of slices reads A's columns once
-// per share (four times at d = 4e4).  Beyond two shares the launches are row-major instead -- all
-// row blocks of as many slices as the device holds -- so A's columns are read once over all
-// launches, and the eight XCDs, which stream the same columns of the same rows at about the same
-// time, find each other's fetches in the memory-side cache.  (Measured at m = 1e6: d = 4e4,
-// n = 2000 took 14.8 ms against 16.0 ms in slice-per-XCD launches; d = 2e4, n = 1000, two shares,
-// took 8.0 ms against 6.4 ms, so it stays slice-per-XCD.)
+// Slice-per-XCD launches, when one XCD's CUs hold every sketch row of a slice: each XCD takes its
+// own slice of a group of eight, so a row of A is fetched into each XCD's L2 once and shared there
+// by the CUs that need it.  Larger d takes row-major launches -- all row blocks of as many slices
+// as the device holds -- so A's columns are read once over all launches.  When the launch's slice
+// count divides 8 and each XCD can hold its share, the slices are kept apart by XCD (slice j on the
+// XCDs x with x % ns == j), so the nonzeros of a row of A still meet in one of a few L2s: at
+// m = 4e6, n = 2000, d = 4e4 (two slices per launch, each on four XCDs) the sketch took 48.6 ms
+// against 58.1 ms with the row blocks of both slices dealt over all eight XCDs, at m = 1e6,
+// n = 1000, d = 2e4 (four slices, two XCDs each) 5.73 ms against 6.46 ms with two slice-per-XCD
+// launches per group of eight slices.  Row-major launches meet at a work-group barrier every
+// step when a group has at least 128 list entries per step (d = 2e4), else every kWinRowMajorSync
+// steps (d = 3e4 and 4e4: 11.10 and 48.6 ms, against 11.65 and 50.9 every step).
 template <typename OT>
 hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int64_t lda,
                       const double *b, double scale, OT *B, int64_t ldb, OT *Sb, int64_t ldsb,
@@ -973,21 +993,25 @@ hipError_t gather_win(hipStream_t s, int64_t d, int64_t n, const double *A, int6
     const int32_t nslice = (int32_t)((n + (b ? 1 : 0) + 63) / 64);
     const int64_t ngroups = (d + w.rw - 1) / w.rw;
     const int64_t nrb = (ngroups + kWinWaves - 1) / kWinWaves;
-    const int64_t launches = (nrb + w.cus - 1) / w.cus;            // per group of eight slices
     hipError_t e = hipSuccess;
-    if (nrb <= 2 * (int64_t)w.cus) {     // row-major measured slower with two shares per group
+    if (nrb <= (int64_t)w.cus) {
         for (int32_t s0 = 0; s0 < nslice && e == hipSuccess; s0 += 8)
-            for (int64_t l = 0; l < launches && e == hipSuccess; ++l) {
-                const int64_t rb0 = nrb * l / launches, rb1 = nrb * (l + 1) / launches;
-                e = gather_win_launch(s, dim3((unsigned)(8 * (rb1 - rb0))), d, n, nslice, s0, rb0, 0, A, lda,
-                                      b, scale, B, ldb, Sb, ldsb, w);
-            }
+            e = gather_win_launch(s, dim3((unsigned)(8 * nrb)), d, n, nslice, s0, 0, 0, A, lda, b, scale, B, ldb,
+                                  Sb, ldsb, w);
     } else {
+        // list entries of one group per barrier step: rw rows x (kWinPerStep kWinLen zeta / d)
+        const int64_t per_step = (int64_t)w.rw * kWinPerStep * kWinLen * w.zeta / d;
+        const int32_t sync_every = per_step >= 128 ? 1 : kWinRowMajorSync;
         const int64_t per_launch = std::max<int64_t>(1, (int64_t)8 * w.cus / nrb);   // slices
         for (int32_t s0 = 0; s0 < nslice && e == hipSuccess; s0 += (int32_t)per_launch) {
             const int64_t ns = std::min<int64_t>(per_launch, nslice - s0);
-            e = gather_win_launch(s, dim3((unsigned)(ns * nrb)), d, n, nslice, s0, 0, nrb, A, lda, b, scale,
-                                  B, ldb, Sb, ldsb, w);
+            const int64_t per_xcd = (ns == 1 || ns == 2 || ns == 4 || ns == 8) ? (nrb + 8 / ns - 1) / (8 / ns) : 0;
+            if (per_xcd > 0 && per_xcd <= (int64_t)w.cus)
+                e = gather_win_launch(s, dim3((unsigned)(8 * per_xcd)), d, n, nslice, s0, 0, nrb, A, lda, b, scale,
+                                      B, ldb, Sb, ldsb, w, (int32_t)ns, sync_every);
+            else
+                e = gather_win_launch(s, dim3((unsigned)(ns * nrb)), d, n, nslice, s0, 0, nrb, A, lda, b, scale,
+                                      B, ldb, Sb, ldsb, w, 0, sync_every);
         }
     }
     if (e != hipSuccess) return e;
