@@ -497,6 +497,17 @@ __global__ void k_zero_u32(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
+// Work-group id -> (major, minor) tile for a grid of 8 ceil(nmajor / 8) nminor work-groups: every
+// tile of one major index (a row block or chunk, which shares its rows of V) runs on one XCD
+// (work-group i runs on XCD i mod 8), minor indices in order.  False for the padding past nmajor.
+__device__ __forceinline__ bool xcd_tile(int64_t id, int64_t nmajor, int64_t nminor, int64_t &major, int64_t &minor)
+{
+    const int64_t j = id / 8;
+    major = id % 8 + 8 * (j / nminor);
+    minor = j % nminor;
+    return major < nmajor;
+}
+
 // P[ch][a][c] = sum over the rows r of chunk ch of V[r][a] X[r][c], for X = [V | C] (column c < kNB
 // of X is column c of V, column c >= kNB is column c - kNB of C), a < kNB, c < nx = kNB + nc.
 // Work-group: 64 columns of X.  Its four waves take interleaved groups of 4 rows of the chunk
@@ -505,11 +516,12 @@ __global__ void k_zero_u32(unsigned *p, int n)
 template <typename E>
 __global__ void __launch_bounds__(256)
 k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__restrict__ C,
-             int64_t ldc, int64_t nx, int64_t ldo, E *__restrict__ P)
+             int64_t ldc, int64_t nx, int64_t ldo, E *__restrict__ P, int64_t nch)
 {
     __shared__ E s_acc[4][kNB][64 + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t ch = blockIdx.x;
+    int64_t ch, cblk;
+    if (!xcd_tile(blockIdx.x, nch, (nx + 63) / 64, ch, cblk)) return;
     const int64_t r_lo = ch * chunk;
     const int64_t r_hi = (r_lo + chunk < rows) ? r_lo + chunk : rows;
     const int kk = lane >> 4, ii = lane & 15;
@@ -519,7 +531,7 @@ k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__re
     bool cok[4];
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb) {
-        const int64_t col = (int64_t)blockIdx.y * 64 + 16 * sb + ii;
+        const int64_t col = cblk * 64 + 16 * sb + ii;
         cok[sb] = col < nx;
         src[sb] = (col < kNB) ? V + col : C + (col - kNB);
         lds[sb] = (col < kNB) ? (int64_t)kNB : ldc;
@@ -560,7 +572,7 @@ k_vx_partial(int64_t rows, int64_t chunk, const E *__restrict__ V, const E *__re
     __syncthreads();
     for (int e = threadIdx.x; e < kNB * 64; e += blockDim.x) {
         const int a = e / 64, c = e % 64;
-        const int64_t col = (int64_t)blockIdx.y * 64 + c;
+        const int64_t col = cblk * 64 + c;
         if (col >= nx) continue;
         const E t = ((s_acc[0][a][c] + s_acc[1][a][c]) + s_acc[2][a][c]) + s_acc[3][a][c];
         P[(ch * kNB + a) * ldo + col] = t;
@@ -673,8 +685,10 @@ k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restric
            int64_t ldz, E *__restrict__ C, int64_t ldc)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * wave;
-    const int64_t c0 = (int64_t)blockIdx.y * 64;
+    int64_t rblk, cblk;
+    if (!xcd_tile(blockIdx.x, (rows + 63) / 64, (nc + 63) / 64, rblk, cblk)) return;
+    const int64_t r0 = rblk * 64 + 16 * wave;
+    const int64_t c0 = cblk * 64;
     const int kk = lane >> 4, ii = lane & 15;
     const int64_t ra = r0 + ii;
     const bool ra_ok = ra < rows;
@@ -939,13 +953,13 @@ void trailing_update(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, 
     const int nch = (int)ceil_div(rows, chunk);
     const int64_t ldo = ceil_div(n + 1, 64) * 64 + 64;
     const E *C0 = qb.W + p0 * ldw + c0;
-    hipLaunchKernelGGL(k_vx_partial<E>, dim3(nch, (unsigned)ceil_div(kNB + nc, 64)), dim3(256), 0, s,
-                       rows, chunk, V, C0, ldw, (int64_t)kNB + nc, ldo, Yp);
+    hipLaunchKernelGGL(k_vx_partial<E>, dim3((unsigned)(8 * ceil_div(nch, 8) * ceil_div(kNB + nc, 64))), dim3(256), 0,
+                       s, rows, chunk, V, C0, ldw, (int64_t)kNB + nc, ldo, Yp, (int64_t)nch);
     hipLaunchKernelGGL(k_sum_partials<E>, dim3((unsigned)ceil_div(kNB + nc, 64), kNB / 4), dim3(256), 0, s,
                        nch, ldo, (int64_t)kNB + nc, Yp);
     hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, 1, ldo, Yp,
                        qb.tau, p0, nbp, nc, Z, ldw);
-    hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(nc, 64)),
+    hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)(8 * ceil_div(ceil_div(rows, 64), 8) * ceil_div(nc, 64))),
                        dim3(256), 0, s, rows, nc, V, Z, ldw, qb.W + p0 * ldw + c0, ldw);
 }
 
