@@ -11,7 +11,8 @@
  * Conventions shared by every entry point
  *  - Matrices are row-major: element (i, j) of a matrix with leading dimension ld is at [i*ld + j].
  *  - All array arguments are DEVICE pointers on the context's GPU, allocated and freed by the
- *    caller; they must be 8-byte aligned.  The library owns only its internal workspace.
+ *    caller; they must be 8-byte aligned.  The library owns only its internal workspace (and
+ *    the side stream of ls_create's note).
  *  - `stream` is a hipStream_t (NULL: the device's null stream).  Every call enqueues its work on
  *    that stream and returns without waiting, except ls_sync and ls_solve (which waits to report).
  *  - Argument errors are reported synchronously (LS_ERR_ARG) before anything is enqueued.
@@ -53,9 +54,12 @@ typedef struct ls_ctx ls_ctx;
 /* Context: binds a GPU, its compiled kernels, a growable workspace and the status word.
  * device >= 0 selects a GPU.  device = -1 creates a host-only context that validates arguments
  * and then returns LS_ERR_DEVICE from every compute call (for testing argument checks without a
- * GPU).  Returns LS_ERR_DEVICE if the GPU cannot be used. */
+ * GPU).  Returns LS_ERR_DEVICE if the GPU cannot be used.  The first QR of a large sketch
+ * (d*n >= 6e7, cooperative panels) also creates one non-blocking side stream and two events in
+ * the context; that QR's trailing updates run partly on it, joined back into the caller's stream
+ * by events before the call's later work, so ordering on the caller's stream is unchanged. */
 ls_status ls_create(int device, ls_ctx **out);
-void ls_destroy(ls_ctx *ctx);                       /* frees the workspace; NULL is a no-op   */
+void ls_destroy(ls_ctx *ctx);         /* frees the workspace, side stream, events; NULL is a no-op */
 const char *ls_last_error(const ls_ctx *ctx);       /* detail of the last failure, never NULL  */
 ls_status ls_limits(int32_t *max_zeta, int32_t *max_n);
 
