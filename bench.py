@@ -23,7 +23,8 @@ Other workloads (one JSON line each):
     --workload served_512         512 FP64 problems (m log-uniform on [2e4, 2e5], n in {32, 64, 128,
                                   256}, kappa log-uniform on [1e2, 1e12], ||r|| = 1e-6, d = 20 n, q = 40)
                                   through the served stream, arriving Poisson at 200/s and all at
-                                  once (saturation), against ls_solve one request at a time
+                                  once (saturation), against ls_solve one request at a time; then
+                                  the same with mixed precision (served and ls_solve)
 """
 from __future__ import annotations
 
@@ -377,8 +378,11 @@ def bench_served(args, w):
           f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
     q = w["q"]
 
-    def served(poisson: bool):
+    names = ["fp64", "mixed", "fell_back_condest", "fell_back_growth"]
+
+    def served(poisson: bool, precision: int = 0):
         srv = ls.Server(0, budget_bytes=200 << 30, max_active=len(reqs))
+        srv.set_precision(precision)
         xs = [torch.empty(r["n"], dtype=torch.float64, device="cuda") for r in reqs]
         # warm-up: one small request compiles nothing but touches every code path once
         spec, A, b, _ = probs[0]
@@ -403,12 +407,16 @@ def bench_served(args, w):
         for t in tickets:
             t0, _, _, t3 = srv.times(t)
             lat.append(t3 - t0)
+        used = [srv.precision(t) for t in tickets]
         stats = srv.stats()
         srv.close()
-        return {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
-                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
-                "rounds": stats["rounds"], "failed": sum(1 for s_ in status if s_ != ls.LS_OK),
-                "footprint_peak_GB": stats["footprint_peak"] / 1e9}, xs
+        out = {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+               "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
+               "rounds": stats["rounds"], "failed": sum(1 for s_ in status if s_ != ls.LS_OK),
+               "footprint_peak_GB": stats["footprint_peak"] / 1e9}
+        if precision:
+            out["precision_used"] = {nm: sum(1 for u in used if u == k) for k, nm in enumerate(names)}
+        return out, xs
 
     def baseline(poisson: bool, precision: int = 0):
         ctx = ls.Context(0)
@@ -435,7 +443,6 @@ def bench_served(args, w):
         out = {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99)}
         if precision:
-            names = ["fp64", "mixed", "fell_back_condest", "fell_back_growth"]
             out["precision_used"] = {nm: sum(1 for u in used if u == k) for k, nm in enumerate(names)}
             out["per_request"] = [{"n": r["n"], "kappa": r["kappa"], "used": names[u]} for r, u in zip(reqs, used)]
         return out, xs
@@ -449,8 +456,12 @@ def bench_served(args, w):
     print(f"[bench] ls_solve saturation: {out['ls_solve_saturation']}", file=sys.stderr, flush=True)
     out["ls_solve_poisson"], _ = baseline(True)
     print(f"[bench] ls_solve poisson: {out['ls_solve_poisson']}", file=sys.stderr, flush=True)
-    # The mixed-precision arm: the served stream runs FP64 only, so the mixed form is ls_solve with
-    # LS_OPT_PRECISION = 1, one request at a time, with the precision each request ended in.
+    # The mixed-precision arm: the served stream with mixed precision (saturation and Poisson), and
+    # ls_solve with LS_OPT_PRECISION = 1 one request at a time (whose bits it must return).
+    out["served_mixed_saturation"], xs_smixed = served(False, precision=1)
+    print(f"[bench] served mixed saturation: {out['served_mixed_saturation']}", file=sys.stderr, flush=True)
+    out["served_mixed_poisson"], _ = served(True, precision=1)
+    print(f"[bench] served mixed poisson: {out['served_mixed_poisson']}", file=sys.stderr, flush=True)
     out["ls_solve_mixed_saturation"], xs_mixed = baseline(False, precision=1)
     print(f"[bench] ls_solve mixed saturation: "
           f"{ {k: v for k, v in out['ls_solve_mixed_saturation'].items() if k != 'per_request'} }",
@@ -471,13 +482,16 @@ def bench_served(args, w):
         "speedup_saturation_vs_ls_solve": out["served_saturation"]["solves_per_s"] / out["ls_solve_saturation"]["solves_per_s"],
         "bitwise_equal_to_ls_solve": same,
         "forward_error_max": max(fe),
+        "mixed_vs_fp64_served_speedup": (out["served_mixed_saturation"]["solves_per_s"]
+                                         / out["served_saturation"]["solves_per_s"]),
+        "served_mixed_bitwise_equal_to_ls_solve_mixed": all(torch.equal(a, b_) for a, b_ in zip(xs_smixed, xs_mixed)),
         "mixed_vs_fp64_ls_solve_speedup": (out["ls_solve_mixed_saturation"]["solves_per_s"]
                                            / out["ls_solve_saturation"]["solves_per_s"]),
         "forward_error_max_mixed": max(fe_mixed),
         "forward_error_mixed_over_fp64_max": max(a / max(b_, 1e-300) for a, b_ in zip(fe_mixed, fe)),
         **out,
     }
-    del probs, xs_sat, xs_base, xs_mixed
+    del probs, xs_sat, xs_base, xs_mixed, xs_smixed
     release_device()
     print(json.dumps(rec), flush=True)
 

@@ -218,8 +218,9 @@ ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float
                                const double *c, double *d);
 
 /* ---- Served stream (many independent solves resident on one GPU) -------------------------------
- * A server solves submitted problems with ls_solve's FP64 algorithm (zeta = 8, fixed q, plain update)
- * and returns, for each, the same bits ls_solve returns for it alone.  Problems are admitted first
+ * A server solves submitted problems with ls_solve's algorithm (zeta = 8, fixed q, plain update; FP64,
+ * or mixed precision after ls_server_set_precision) and returns, for each, the same bits ls_solve
+ * returns for it alone with the same precision option.  Problems are admitted first
  * in, first out while the footprint stays within `budget_bytes` and at most `max_active` are
  * admitted.  The footprint counts, for every admitted problem, its resident bytes (A and b, 8mn + 8m,
  * plus its device block: R, R^T, pass partials, c) and the workspaces the four setup lanes hold
@@ -253,6 +254,14 @@ ls_status ls_server_submit(ls_server *server, int64_t m, int64_t n, const double
 /* Waits until the request is finished (timeout_s < 0: no limit) and stores its status (LS_OK, or a
  * deferred error of that problem alone) in *result; LS_ERR_TIMEOUT if it is still running. */
 ls_status ls_server_wait(ls_server *server, int64_t ticket, double timeout_s, ls_status *result);
+/* Arithmetic of the requests submitted after this call: LS_PRECISION_FP64 (the default) or
+ * LS_PRECISION_MIXED, the mixed-precision variant of ls_solve with LS_OPT_PRECISION = 1 (see "Mixed
+ * precision" above): the FP64 sketch, an FP32 QR and FP32 R-solves, FP64 passes and updates.  Its setup waits on the host once, in the
+ * scheduler thread, for the fallback decision; a request whose growth monitor fires in the rounds
+ * is queued again and solved in FP64.  LS_ERR_ARG for any other value. */
+ls_status ls_server_set_precision(ls_server *server, int32_t precision);
+/* The precision a request's result comes from (LS_PRECISION_*); final once the request is finished. */
+ls_status ls_server_request_precision(ls_server *server, int64_t ticket, int32_t *used);
 /* times[0..3]: submission, admission, first round, completion (seconds since ls_server_create;
  * completion is when the scheduler saw the last round end). */
 ls_status ls_server_request_info(ls_server *server, int64_t ticket, double *times);

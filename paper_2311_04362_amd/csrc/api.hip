@@ -231,7 +231,7 @@ static ls_status iterate_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, 
     update_params(ctx, n, d, mode, alpha, beta);
     StopArgs st;
     if (ctx->stop) {
-        HIP_TRY(ctx, launch_estimators(s, n, R, n, RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+        HIP_TRY(ctx, launch_estimators(s, n, R, n, RT, ctx->seed + kEstimatorSeedOffset, est_work, ib.scal), "estimators");
         HIP_TRY(ctx, launch_stop_init(s, ib.state), "stop init");
         st.state = ib.state;
         st.scal = ib.scal;
@@ -334,7 +334,7 @@ static ls_status solve_fp64(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, co
 // x <- x + R32^{-1} R32^{-T} B^T (S b - B x) on the FP64 sketch is about 2 condest u_32, so
 // ceil(ln(1e-9) / ln(2 condest u_32)) steps, clamped to [2, 8], take the FP32 solution (about
 // 1e-7 relative) to FP64 accuracy.
-static int32_t mixed_start_steps(double condest)
+int32_t mixed_start_steps(double condest)
 {
     const double rho = 2.0 * condest * 0x1p-24;
     if (!(rho > 0.0)) return 2;
@@ -382,7 +382,7 @@ static ls_status solve_mixed(ls_ctx *ctx, hipStream_t s, int64_t m, int64_t n, c
     HIP_TRY(ctx, launch_qr(s, d, n, qb, ctx->status, ctx->qr_panel == 1, la), "QR kernels");
     HIP_TRY(ctx, launch_extract_r(s, n, qb, R, n, ctx->status), "extract R");
     HIP_TRY(ctx, launch_back_substitution(s, n, R, n, qb.RT, qb.qtb, x, ctx->status), "x0 solve");
-    HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + 0x632BE59BD9B4E019ULL, est_work, ib.scal), "estimators");
+    HIP_TRY(ctx, launch_estimators(s, n, R, n, qb.RT, ctx->seed + kEstimatorSeedOffset, est_work, ib.scal), "estimators");
     double scv[4];
     HIP_TRY(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status");
     HIP_TRY(ctx, hipMemcpyAsync(scv, ib.scal, sizeof(scv), hipMemcpyDeviceToHost, s), "read estimates");

@@ -11,7 +11,10 @@
 #include "ls.h"
 
 // Deferred device status bits, OR-ed into the context's status word by kernels.
-enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4, ST_TIMEOUT = 8 };
+enum : int32_t { ST_RANK = 1, ST_NONFINITE = 2, ST_DIVERGED = 4, ST_TIMEOUT = 8,
+                 // served mixed precision only (a request's own status word, never a context's):
+                 // the growth monitor froze x, the server repeats the request in FP64
+                 ST_GROWTH = 16 };
 
 // Look-ahead of the blocked QR: a second stream of the context and two events.  After each panel
 // the next panel's columns are updated on the caller's stream, which then factors that panel,
@@ -250,12 +253,16 @@ ls_status pass_scratch_attach(ls_ctx *ctx);
 struct ServeSlot {
     const double *A, *b;
     double *x;                  // x_i in, x_{i+1} out (the caller's buffer)
-    const double *R, *RT;       // n x n, ld n, zero strict lower triangle; RT = R^T
+    const void *R, *RT;         // n x n, ld n, zero strict lower triangle; RT = R^T (FP64, or FP32
+                                // when r32)
     double *part, *part_rr;     // P x n, P
     double *c, *rr;             // n, 1
     int64_t m, n, lda;
     int32_t P, pass_base, red_base, cls;
     int32_t *status;            // the problem's own status word
+    int32_t r32;                // 1: mixed precision (FP32 factor, growth monitor)
+    int32_t *gstate;            // r32: [0] frozen, [1] steps made, [2] monitor fired, [3] growth run
+    double *gprev;              // r32: ||r||^2 of the previous step
 };
 int32_t pass_class(int64_t n);  // pass variant of a problem with n columns (0..8)
 // Pass of every slot of class `cls` (work-groups listed in wg_slot, total_wg of them), reductions of
@@ -275,6 +282,11 @@ hipError_t launch_gradient(hipStream_t s, int64_t m, int64_t n, const double *A,
                            double *rnorm2, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                            const double *dx = nullptr, double *ad_out = nullptr,
                            const int32_t *done = nullptr);
+// The Section 3.3 estimators draw their start vector from the stream seed + this offset.
+constexpr uint64_t kEstimatorSeedOffset = 0x632BE59BD9B4E019ULL;
+// Refinement steps on the FP64 sketch that take the FP32 sketch-and-solve start of the mixed
+// path to FP64 accuracy, from condest of the FP32 factor (2 to 8).
+int32_t mixed_start_steps(double condest);
 // Stopping rule of Section 3.3 evaluated on the device (see k_solve).
 struct StopArgs {
     int32_t *state = nullptr;   // [0] done flag, [1] updates made, [2] fall back to FP64, [3] growth run

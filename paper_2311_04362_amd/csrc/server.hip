@@ -7,9 +7,17 @@
 // of a round is shared by everything resident.  Each problem's arithmetic is that of ls_solve on it
 // alone: its result does not depend on what else is resident.
 //
+// Mixed precision (ls_server_set_precision): a request's setup runs in two parts on its lane.  The
+// first forms the FP64 sketch, factors its FP32 rounding and takes the FP32 start and condest; the
+// scheduler then reads the status word and condest and enqueues either the FP64 factorization of
+// the same sketch (the condest fallback) or the refinement steps of the start on the FP64 sketch.
+// Rounds solve with the FP32 factor under the growth monitor; a request whose monitor fires is
+// queued again as an FP64 request.  Each outcome is ls_solve's with LS_OPT_PRECISION = 1.
+//
 // A scheduler thread owned by the server does all device work; ls_server_submit and ls_server_wait
 // may be called from any host thread.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
@@ -51,7 +59,12 @@ struct Req {
     double *R = nullptr, *RT = nullptr, *part = nullptr, *part_rr = nullptr, *c = nullptr, *rr = nullptr;
     int32_t *status = nullptr;
     int32_t P = 1;
-    int32_t *status_host = nullptr;    // pinned copy, written by the setup and by the last round
+    int32_t *status_host = nullptr;    // pinned: [0] status word (setup, last round), [2..3] condest
+    int32_t prec = LS_PRECISION_FP64;  // arithmetic of the next setup: FP64 or mixed
+    int32_t used = LS_PRECISION_FP64;  // what the result comes from (LS_PRECISION_*)
+    int32_t phase = 0;                 // mixed setup: 1 FP32 factor enqueued, 2 start or fallback
+    int32_t *gstate = nullptr;         // growth monitor of the FP32 rounds (ServeSlot::gstate)
+    double *gprev = nullptr;
     hipEvent_t ev = nullptr;           // end of setup, then end of the last round
     int lane = -1;                     // setup lane while in setup
 };
@@ -63,6 +76,7 @@ struct ls_server {
     int64_t budget = 0;
     int32_t max_active = 0;
     int32_t zeta = 8;
+    std::atomic<int32_t> precision{LS_PRECISION_FP64};   // of requests submitted from now on
     Clock::time_point t0;
     hipStream_t s_serve = nullptr;
     // setup lanes: a stream and a workspace (sketch and QR of one problem at a time) each
@@ -116,8 +130,9 @@ namespace {
 
 double seconds_since(const ls_server *sv) { return std::chrono::duration<double>(Clock::now() - sv->t0).count(); }
 
-// The per-problem device block (R, R^T, pass partials, c, ||r||^2, status word), carved from `base`
-// (nullptr: sizing only).  Returns its size in bytes.
+// The per-problem device block (R, R^T, pass partials, c, ||r||^2, status word, growth monitor),
+// carved from `base` (nullptr: sizing only).  R and R^T have room for an FP64 factor; an FP32 one
+// uses the first half of each.  Returns its size in bytes.
 size_t carve_req(Req *r, char *base)
 {
     Arena ar;
@@ -129,6 +144,8 @@ size_t carve_req(Req *r, char *base)
     r->c = ar.take<double>((size_t)r->n);
     r->rr = ar.take<double>(1);
     r->status = ar.take<int32_t>(1);
+    r->gstate = ar.take<int32_t>(4);
+    r->gprev = ar.take<double>(1);
     return ar.off + 256;
 }
 
@@ -140,16 +157,40 @@ int64_t resident_bytes(Req *r)
     return 8 * r->m * r->n + 8 * r->m + (int64_t)carve_req(r, nullptr);
 }
 
-// Workspace a setup lane needs for the sketch and QR of a problem (the same carve enqueue_setup makes).
-int64_t setup_bytes(int64_t m, int64_t n, int64_t d, int32_t zeta)
-{
+// A setup lane's workspace for one problem: embedding and CSR, the FP64 QR work matrix; for mixed
+// precision also the FP32 work matrix, S b apart, the sketch-sized pass buffers of the start's
+// refinement steps and the estimators' work vectors.
+struct SetupBufs {
     SketchBufs sb{};
     QrBufs qb{};
+    QrBufs32 qb32{};
+    IterBufs ib{};
+    double *Sb = nullptr;
+    float *est = nullptr;
+};
+
+void carve_setup(Arena &ar, int64_t m, int64_t n, int64_t d, int32_t zeta, int32_t prec, SetupBufs &w)
+{
+    sketch_bufs(ar, m, d, zeta, w.sb);
+    qr_bufs(ar, d, n, w.qb);
+    if (prec == LS_PRECISION_MIXED) {
+        qr_bufs(ar, d, n, w.qb32);
+        iter_bufs(ar, d, n, w.ib, false);
+        w.Sb = ar.take<double>((size_t)d);
+        w.est = ar.take<float>((size_t)3 * (size_t)n);
+    }
+}
+
+// Workspace a setup lane needs for a problem (the same carve enqueue_setup makes).
+int64_t setup_bytes(int64_t m, int64_t n, int64_t d, int32_t zeta, int32_t prec)
+{
+    SetupBufs w;
     Arena ar;
-    sketch_bufs(ar, m, d, zeta, sb);
-    qr_bufs(ar, d, n, qb);
+    carve_setup(ar, m, n, d, zeta, prec, w);
     return (int64_t)ar.off + 256;
 }
+
+double *condest_host(Req *r) { return reinterpret_cast<double *>(r->status_host + 2); }
 
 bool hip_ok(ls_server *sv, hipError_t e, const char *what)
 {
@@ -251,20 +292,17 @@ int pick_lane(const ls_server *sv, int64_t need)
     return best;
 }
 
-// Enqueue sketch, QR, R, R^T and x_0 of one problem on a free setup lane (as ls_solve does), then the
-// copy of its status word and the event the scheduler waits for.
+// Enqueue the setup of one problem on a free setup lane, then the copy of its status word and the
+// event the scheduler waits for.  FP64: sketch, QR, R, R^T and x_0 (as ls_solve does).  Mixed: the
+// FP64 sketch (S b apart), the FP32 QR of its rounding, R, R^T, the FP32 start and the estimators,
+// with condest copied out beside the status word; enqueue_mixed_rest follows.
 bool enqueue_setup(ls_server *sv, Req *r, int lane)
 {
     ls_server::Lane &ln = sv->lanes[lane];
     hipStream_t s = ln.s;
-    SketchBufs sb{};
-    QrBufs qb{};
-    auto carve = [&](Arena &ar) {
-        sketch_bufs(ar, r->m, r->d, sv->zeta, sb);
-        qr_bufs(ar, r->d, r->n, qb);
-    };
+    SetupBufs w;
     Arena sizing;
-    carve(sizing);
+    carve_setup(sizing, r->m, r->n, r->d, sv->zeta, r->prec, w);
     const int64_t room = sv->budget - sv->footprint_now + (int64_t)ln.ws_bytes;
     if (!ensure_setup_ws(sv, ln, sizing.off + 256, room)) {
         r->result = LS_ERR_ALLOC;
@@ -272,23 +310,78 @@ bool enqueue_setup(ls_server *sv, Req *r, int lane)
     }
     Arena real;
     real.base = static_cast<char *>(ln.ws);
-    carve(real);
-    const int64_t n = r->n;
+    carve_setup(real, r->m, r->n, r->d, sv->zeta, r->prec, w);
+    const int64_t n = r->n, d = r->d;
+    const double scale = 1.0 / std::sqrt((double)sv->zeta);
     bool ok = hip_ok(sv, hipMemsetAsync(r->status, 0, sizeof(int32_t), s), "clear status") &&
-              hip_ok(sv, launch_sparse_sign(s, r->m, r->d, sv->zeta, r->seed, sb), "sparse-sign kernel") &&
-              hip_ok(sv, launch_csr(s, r->m, r->d, sv->zeta, sb), "CSR kernels") &&
-              hip_ok(sv, launch_gather(s, r->d, n, r->A, r->lda, r->b, sb.rowptr, sb.cols,
-                                       1.0 / std::sqrt((double)sv->zeta), qb.W, qb.ldw, qb.W + n, qb.ldw),
-                     "gather kernel") &&
-              // per-column panels: a cooperative grid barrier would have to share the device with
-              // the rounds running on the serve stream (both paths give the same bits)
-              hip_ok(sv, launch_qr(s, r->d, n, qb, r->status, true), "QR kernels") &&
-              hip_ok(sv, launch_extract_r(s, n, qb, r->R, n, r->status), "extract R") &&
-              hip_ok(sv, hipMemcpyAsync(r->RT, qb.RT, sizeof(double) * (size_t)(n * n), hipMemcpyDeviceToDevice, s), "copy R^T") &&
-              hip_ok(sv, launch_back_substitution(s, n, r->R, n, qb.RT, qb.qtb, r->x, r->status), "x0 solve") &&
-              hip_ok(sv, hipMemcpyAsync(r->status_host, r->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status") &&
-              hip_ok(sv, hipEventRecord(r->ev, s), "record setup event");
-    return ok;
+              hip_ok(sv, launch_sparse_sign(s, r->m, d, sv->zeta, r->seed, w.sb), "sparse-sign kernel") &&
+              hip_ok(sv, launch_csr(s, r->m, d, sv->zeta, w.sb), "CSR kernels");
+    // per-column panels: a cooperative grid barrier would have to share the device with the rounds
+    // running on the serve stream (both paths give the same bits)
+    if (r->prec == LS_PRECISION_MIXED) {
+        float *R = reinterpret_cast<float *>(r->R), *RT = reinterpret_cast<float *>(r->RT);
+        ok = ok &&
+             hip_ok(sv, launch_gather(s, d, n, r->A, r->lda, r->b, w.sb.rowptr, w.sb.cols, scale, w.qb.W,
+                                      w.qb.ldw, w.Sb, 1), "gather kernel") &&
+             hip_ok(sv, launch_round_sketch(s, d, n, w.qb, w.Sb, w.qb32), "round sketch") &&
+             hip_ok(sv, launch_qr(s, d, n, w.qb32, r->status, true), "QR kernels") &&
+             hip_ok(sv, launch_extract_r(s, n, w.qb32, R, n, r->status), "extract R") &&
+             hip_ok(sv, hipMemcpyAsync(RT, w.qb32.RT, sizeof(float) * (size_t)(n * n), hipMemcpyDeviceToDevice, s), "copy R^T") &&
+             hip_ok(sv, launch_back_substitution(s, n, R, n, RT, w.qb32.qtb, r->x, r->status), "x0 solve") &&
+             hip_ok(sv, launch_estimators(s, n, R, n, RT, r->seed + kEstimatorSeedOffset, w.est, w.ib.scal), "estimators") &&
+             hip_ok(sv, hipMemcpyAsync(condest_host(r), w.ib.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s), "read condest");
+        r->phase = 1;
+    } else {
+        ok = ok &&
+             hip_ok(sv, launch_gather(s, d, n, r->A, r->lda, r->b, w.sb.rowptr, w.sb.cols, scale, w.qb.W,
+                                      w.qb.ldw, w.qb.W + n, w.qb.ldw), "gather kernel") &&
+             hip_ok(sv, launch_qr(s, d, n, w.qb, r->status, true), "QR kernels") &&
+             hip_ok(sv, launch_extract_r(s, n, w.qb, r->R, n, r->status), "extract R") &&
+             hip_ok(sv, hipMemcpyAsync(r->RT, w.qb.RT, sizeof(double) * (size_t)(n * n), hipMemcpyDeviceToDevice, s), "copy R^T") &&
+             hip_ok(sv, launch_back_substitution(s, n, r->R, n, w.qb.RT, w.qb.qtb, r->x, r->status), "x0 solve");
+        r->phase = 0;
+    }
+    return ok && hip_ok(sv, hipMemcpyAsync(r->status_host, r->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status") &&
+           hip_ok(sv, hipEventRecord(r->ev, s), "record setup event");
+}
+
+// Second part of a mixed setup, on the same lane once the first has finished (its workspace still
+// holds the FP64 sketch): ls_solve's decision from the FP32 factor's status word and condest.  Falls
+// back (FP64 QR of the same sketch, R, R^T, x_0) when the FP32 QR flagged R or condest u_32 > 0.05;
+// otherwise refines the FP32 start on the FP64 sketch (mixed_start_steps) and clears the growth
+// monitor.
+bool enqueue_mixed_rest(ls_server *sv, Req *r)
+{
+    ls_server::Lane &ln = sv->lanes[r->lane];
+    hipStream_t s = ln.s;
+    SetupBufs w;
+    Arena real;
+    real.base = static_cast<char *>(ln.ws);
+    carve_setup(real, r->m, r->n, r->d, sv->zeta, LS_PRECISION_MIXED, w);
+    const int64_t n = r->n, d = r->d;
+    const int32_t st0 = r->status_host[0];
+    const double cond = *condest_host(r);
+    bool ok;
+    if ((st0 & (ST_RANK | ST_NONFINITE)) || !(cond * 0x1p-24 <= 0.05)) {
+        r->used = LS_PRECISION_FELL_BACK_COND;
+        ok = hip_ok(sv, hipMemsetAsync(r->status, 0, sizeof(int32_t), s), "clear status") &&
+             hip_ok(sv, launch_set_rhs(s, d, n, w.Sb, w.qb), "set rhs") &&
+             hip_ok(sv, launch_qr(s, d, n, w.qb, r->status, true), "QR kernels") &&
+             hip_ok(sv, launch_extract_r(s, n, w.qb, r->R, n, r->status), "extract R") &&
+             hip_ok(sv, hipMemcpyAsync(r->RT, w.qb.RT, sizeof(double) * (size_t)(n * n), hipMemcpyDeviceToDevice, s), "copy R^T") &&
+             hip_ok(sv, launch_back_substitution(s, n, r->R, n, w.qb.RT, w.qb.qtb, r->x, r->status), "x0 solve");
+    } else {
+        r->used = LS_PRECISION_MIXED;
+        const float *R = reinterpret_cast<const float *>(r->R), *RT = reinterpret_cast<const float *>(r->RT);
+        const int32_t k0 = mixed_start_steps(cond);
+        ok = hip_ok(sv, hipMemsetAsync(r->gstate, 0, 4 * sizeof(int32_t), s), "clear growth monitor");
+        for (int32_t k = 0; k < k0 && ok; ++k)
+            ok = hip_ok(sv, launch_gradient(s, d, n, w.qb.W, w.qb.ldw, w.Sb, r->x, w.ib, w.ib.c, nullptr), "start pass") &&
+                 hip_ok(sv, launch_solve_update(s, n, R, n, RT, w.ib.c, r->x, nullptr, nullptr, 1, 1.0, 0.0, r->status), "start solve");
+    }
+    r->phase = 2;
+    return ok && hip_ok(sv, hipMemcpyAsync(r->status_host, r->status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read status") &&
+           hip_ok(sv, hipEventRecord(r->ev, s), "record setup event");
 }
 
 ls_status status_of(int32_t st)
@@ -320,6 +413,23 @@ void finish(ls_server *sv, Req *r, ls_status result, bool recycle = true)
         r->status_host = nullptr;
     }
     sv->cv_done.notify_all();
+}
+
+// Called with the lock held: the growth monitor of a mixed request fired (its x is frozen).  As
+// ls_solve falls back to FP64, the request gives its device block back and queues again, first, as
+// an FP64 request; its result will be reported as LS_PRECISION_FELL_BACK_GROWTH.
+void requeue_fp64(ls_server *sv, Req *r)
+{
+    give_block(sv, r->mem, r->mem_bytes);
+    r->mem = nullptr;
+    sv->footprint_now -= r->footprint;
+    sv->admitted_live -= 1;
+    r->prec = LS_PRECISION_FP64;
+    r->used = LS_PRECISION_FELL_BACK_GROWTH;
+    r->setup = setup_bytes(r->m, r->n, r->d, sv->zeta, LS_PRECISION_FP64);
+    r->rounds = 0;
+    r->st = St::Queued;
+    sv->queue.push_front(r);
 }
 
 // Slot table and work-group maps of the current active set into the next staging buffer, copied to
@@ -366,6 +476,9 @@ bool upload_table(ls_server *sv, int32_t class_wg[kClasses], int32_t class_off[k
         sl.P = r->P;
         sl.cls = pass_class(r->n);
         sl.status = r->status;
+        sl.r32 = r->used == LS_PRECISION_MIXED ? 1 : 0;
+        sl.gstate = r->gstate;
+        sl.gprev = r->gprev;
         sl.red_base = red_wg;
         const int32_t blocks = (int32_t)((r->n + 63) / 64);
         for (int32_t k2 = 0; k2 < blocks; ++k2) stg.wgmap[off++] = i;
@@ -453,11 +566,22 @@ void scheduler(ls_server *sv)
             sv->setup.push_back(r);
             progress = true;
         }
-        // (2) finished setups join the active set (or leave: error, or q = 0)
+        // (2) finished setups join the active set (or leave: error, or q = 0); the first part of a
+        // mixed setup is followed by its second on the same lane
         for (size_t i = 0; i < sv->setup.size();) {
             Req *r = sv->setup[i];
             const hipError_t e = hipEventQuery(r->ev);
             if (e == hipErrorNotReady) { ++i; continue; }
+            if (e == hipSuccess && r->phase == 1) {
+                progress = true;
+                if (enqueue_mixed_rest(sv, r)) { ++i; continue; }
+                // a device error (sv->fatal is set): device work may still be pending
+                sv->setup.erase(sv->setup.begin() + (long)i);
+                sv->lanes[r->lane].busy = false;
+                r->lane = -1;
+                finish(sv, r, LS_ERR_DEVICE, false);
+                continue;
+            }
             sv->setup.erase(sv->setup.begin() + (long)i);
             sv->lanes[r->lane].busy = false;
             r->lane = -1;
@@ -484,7 +608,15 @@ void scheduler(ls_server *sv)
             if (e == hipErrorNotReady) { ++i; continue; }
             sv->finishing.erase(sv->finishing.begin() + (long)i);
             progress = true;
-            finish(sv, r, hip_ok(sv, e, "round event") ? status_of(*r->status_host) : LS_ERR_DEVICE);
+            if (!hip_ok(sv, e, "round event")) {
+                finish(sv, r, LS_ERR_DEVICE);
+                continue;
+            }
+            if (*r->status_host & ST_GROWTH) {
+                requeue_fp64(sv, r);
+                continue;
+            }
+            finish(sv, r, status_of(*r->status_host));
         }
         // (4) one more round of every active problem, if fewer than kRoundsInFlight are queued
         if (!sv->active.empty() && (int)sv->inflight.size() < kRoundsInFlight && sv->fatal == LS_OK) {
@@ -669,8 +801,9 @@ ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A,
     r->m = m;
     r->n = n;
     r->d = d;
+    const int32_t prec = sv->precision.load();
     const int64_t fp = (sv->device >= 0) ? resident_bytes(r.get()) : 8 * m * n + 8 * m;
-    const int64_t su = setup_bytes(m, n, d, sv->zeta);
+    const int64_t su = setup_bytes(m, n, d, sv->zeta, prec);
     std::unique_lock<std::mutex> lk(sv->mu);
     if (fp + su > sv->budget) {
         sv->err = "the problem's footprint (resident bytes and setup workspace) exceeds the server's HBM budget";
@@ -685,7 +818,7 @@ ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A,
     if (!sv->pin_pool.empty()) {
         pin = sv->pin_pool.back();
         sv->pin_pool.pop_back();
-    } else if (hipHostMalloc(&pin, sizeof(int32_t), hipHostMallocDefault) == hipSuccess) {
+    } else if (hipHostMalloc(&pin, 4 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess) {
         sv->pinned_status.push_back(pin);
     } else {
         (void)hipGetLastError();
@@ -707,6 +840,8 @@ ls_status ls_server_submit(ls_server *sv, int64_t m, int64_t n, const double *A,
     r->lda = lda;
     r->q = q;
     r->seed = seed;
+    r->prec = prec;
+    r->used = prec;
     r->A = A;
     r->b = b;
     r->x = x;
@@ -750,7 +885,7 @@ ls_status ls_server_footprint(ls_server *sv, int64_t m, int64_t n, int64_t d, in
     r.n = n;
     r.d = d;
     *resident = (sv->device >= 0) ? resident_bytes(&r) : 8 * m * n + 8 * m;
-    *setup = setup_bytes(m, n, d, sv->zeta);
+    *setup = setup_bytes(m, n, d, sv->zeta, sv->precision.load());
     return LS_OK;
 }
 
@@ -780,6 +915,23 @@ ls_status ls_server_stats(ls_server *sv, int64_t *stats)
     stats[5] = sv->footprint_peak;
     stats[6] = sv->rounds;
     stats[7] = sv->lanes_ws;
+    return LS_OK;
+}
+
+ls_status ls_server_set_precision(ls_server *sv, int32_t precision)
+{
+    if (!sv || (precision != LS_PRECISION_FP64 && precision != LS_PRECISION_MIXED)) return LS_ERR_ARG;
+    sv->precision.store(precision);
+    return LS_OK;
+}
+
+ls_status ls_server_request_precision(ls_server *sv, int64_t ticket, int32_t *used)
+{
+    if (!sv || !used) return LS_ERR_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return LS_ERR_ARG;
+    *used = it->second->used;
     return LS_OK;
 }
 

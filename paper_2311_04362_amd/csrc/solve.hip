@@ -638,30 +638,64 @@ k_solve(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restrict__ R
     if (st_state && threadIdx.x == 0) st_state[1] += 1;
 }
 
-// Served rounds: d = R^{-1} (R^{-T} c) and x += d for every resident problem, one work-group each,
-// with the arithmetic of k_solve (FP64, plain update) on that problem alone.
+// One served problem's step with the arithmetic of k_solve on it alone: FP64 factor, plain update;
+// or FP32 factor (mixed precision) with k_solve's growth monitor, where a residual that grew three
+// rounds in a row by more than a relative 2^-20 (or a non-finite one) freezes x for the rest of the
+// request's rounds and raises ST_GROWTH, so that the server repeats the request in FP64.
+template <typename T, int kSB>
+__device__ __forceinline__ void served_step(const ServeSlot &sl, T *s, SubstLds<T, kSB> &L, double *red)
+{
+    const int64_t n = sl.n;
+    if (sizeof(T) == 4) {
+        int32_t *g = sl.gstate;
+        if (g[0]) return;
+        const double rr = *sl.rr;
+        const int run = (g[1] != 0 && rr > sl.gprev[0] * (1.0 + 0x1p-20)) ? g[3] + 1 : 0;
+        if (run >= 3 || !isfinite(rr)) {
+            if (threadIdx.x == 0) {
+                g[0] = 1;
+                g[2] = 1;
+                atomicOr(sl.status, ST_GROWTH);
+            }
+            return;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            g[3] = run;
+            sl.gprev[0] = rr;
+        }
+    }
+    const T *R = static_cast<const T *>(sl.R), *RT = static_cast<const T *>(sl.RT);
+    const int e = load_rhs<T>(n, sl.c, s, red);
+    zero_pad<T, kSB>(n, s);
+    __syncthreads();
+    fwd_subst<T, kSB, kSolveThreads>(n, R, n, s, L);
+    back_subst<T, kSB, kSolveThreads>(n, R, n, RT, s, L);
+    bool bad = false;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const double dj = (sizeof(T) == 8) ? (double)s[j] : ldexp((double)s[j], e);
+        const double xn = sl.x[j] + dj;
+        sl.x[j] = xn;
+        bad |= !isfinite(xn);
+    }
+    if (bad) atomicOr(sl.status, ST_NONFINITE);
+    if (sizeof(T) == 4 && threadIdx.x == 0) sl.gstate[1] += 1;
+}
+
+// Served rounds: d = R^{-1} (R^{-T} c) and x += d for every resident problem, one work-group each.
+// The FP64 and FP32 substitutions share one LDS block.
 template <int kSB>
 __global__ void __launch_bounds__(kSolveThreads)
 k_solve_served(const ServeSlot *__restrict__ slots)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *s = reinterpret_cast<double *>(smem);
-    __shared__ SubstLds<double, kSB> L;
+    __shared__ __align__(16) unsigned char lds[sizeof(SubstLds<double, kSB>)];
     __shared__ double red[kSolveThreads / 64];
     const ServeSlot &sl = slots[blockIdx.x];
-    const int64_t n = sl.n;
-    (void)load_rhs<double>(n, sl.c, s, red);
-    zero_pad<double, kSB>(n, s);
-    __syncthreads();
-    fwd_subst<double, kSB, kSolveThreads>(n, sl.R, n, s, L);
-    back_subst<double, kSB, kSolveThreads>(n, sl.R, n, sl.RT, s, L);
-    bool bad = false;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        const double xn = sl.x[j] + s[j];
-        sl.x[j] = xn;
-        bad |= !isfinite(xn);
-    }
-    if (bad) atomicOr(sl.status, ST_NONFINITE);
+    if (sl.r32)
+        served_step<float, kSB>(sl, reinterpret_cast<float *>(smem), *reinterpret_cast<SubstLds<float, kSB> *>(lds), red);
+    else
+        served_step<double, kSB>(sl, reinterpret_cast<double *>(smem), *reinterpret_cast<SubstLds<double, kSB> *>(lds), red);
 }
 
 // Section 3.3 estimators, one work-group, in the arithmetic of the factor (T).

@@ -29,7 +29,8 @@ EXPORTS = ["ls_create", "ls_destroy", "ls_last_error", "ls_limits", "ls_set_opti
            "ls_solve_info", "ls_sketch_f32", "ls_qr_sketch_f32", "ls_precond_solve_f32",
            "ls_server_create", "ls_server_destroy", "ls_server_submit", "ls_server_wait",
            "ls_server_request_info", "ls_server_stats", "ls_server_last_error",
-           "ls_gradient_noalloc", "ls_server_footprint"]
+           "ls_gradient_noalloc", "ls_server_footprint", "ls_server_set_precision",
+           "ls_server_request_precision"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -86,6 +87,8 @@ def load():
         "ls_server_stats": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
         "ls_server_last_error": ([_vp], ctypes.c_char_p),
         "ls_server_footprint": ([_vp, _i64, _i64, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], ctypes.c_int),
+        "ls_server_set_precision": ([_vp, _i32], ctypes.c_int),
+        "ls_server_request_precision": ([_vp, _i64, ctypes.POINTER(_i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -283,8 +286,9 @@ class Context:
 
 
 class Server:
-    """A served stream of FP64 solves on one GPU (ls_server_*).  submit() returns a ticket at once;
-    the tensors stay referenced here until wait() has seen the request finish."""
+    """A served stream of solves on one GPU (ls_server_*), FP64 or mixed precision (set_precision).
+    submit() returns a ticket at once; the tensors stay referenced here until wait() has seen the
+    request finish."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 64 << 30, max_active: int = 1024):
         self._L = load()
@@ -332,6 +336,17 @@ class Server:
         self._check(self._L.ls_server_wait(self.h, ticket, timeout, ctypes.byref(res)), "ls_server_wait")
         self._keep.pop(ticket, None)
         return res.value
+
+    def set_precision(self, precision: int):
+        """Arithmetic of later submissions: PRECISION_FP64 or PRECISION_MIXED."""
+        self._check(self._L.ls_server_set_precision(self.h, precision), "ls_server_set_precision")
+
+    def precision(self, ticket: int) -> int:
+        """The precision the request's result comes from (PRECISION_*)."""
+        u = _i32()
+        self._check(self._L.ls_server_request_precision(self.h, ticket, ctypes.byref(u)),
+                    "ls_server_request_precision")
+        return u.value
 
     def times(self, ticket: int):
         """(submitted, admitted, first round, finished), seconds since the server was created."""

@@ -72,12 +72,19 @@ int main()
     check(ls_server_create(-1, int64_t(1) << 40, 64, &sv) == LS_OK && sv, "host-only server");
     const int64_t shapes[][3] = {{4000, 32, 640}, {200000, 256, 5120}, {2000000, 500, 10000},
                                  {1000000, 1000, 20000}, {4000000, 2000, 40000}, {70001, 2048, 41000}};
-    for (const auto &sh : shapes) {
-        int64_t res = 0, su = 0;
-        check(ls_server_footprint(sv, sh[0], sh[1], sh[2], &res, &su) == LS_OK && res > 0 && su > 0, "footprint");
-        int64_t t = 0;
-        check(ls_server_submit(sv, sh[0], sh[1], P, sh[1], P, sh[2], 40, 1, P, &t) == LS_ERR_DEVICE, "submit");
+    const int32_t precs[] = {LS_PRECISION_FP64, LS_PRECISION_MIXED};
+    for (int32_t prec : precs) {
+        check(ls_server_set_precision(sv, prec) == LS_OK, "set precision");
+        for (const auto &sh : shapes) {
+            int64_t res = 0, su = 0;
+            check(ls_server_footprint(sv, sh[0], sh[1], sh[2], &res, &su) == LS_OK && res > 0 && su > 0, "footprint");
+            int64_t t = 0;
+            check(ls_server_submit(sv, sh[0], sh[1], P, sh[1], P, sh[2], 40, 1, P, &t) == LS_ERR_DEVICE, "submit");
+        }
     }
+    check(ls_server_set_precision(sv, 7) == LS_ERR_ARG, "bad precision");
+    int32_t used = 0;
+    check(ls_server_request_precision(sv, 7, &used) == LS_ERR_ARG, "unknown ticket precision");
     int64_t st[8] = {0};
     check(ls_server_stats(sv, st) == LS_OK && st[0] == 0, "stats");
     ls_status r = LS_OK;

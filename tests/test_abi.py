@@ -236,5 +236,19 @@ def test_server_argument_errors(L):
         assert su_b.value >= 8 * 200 * 11 + 4 * 8 * 1000
         assert L.ls_server_footprint(h, 1000, 10, 9, ctypes.byref(res_b), ctypes.byref(su_b)) == ls.LS_ERR_ARG
         assert L.ls_server_footprint(h, 1000, 10, 200, None, ctypes.byref(su_b)) == ls.LS_ERR_ARG
+        # mixed precision: the setup lane also holds the FP32 work matrix, S b and the start's buffers
+        assert L.ls_server_set_precision(h, 2) == ls.LS_ERR_ARG
+        assert L.ls_server_set_precision(None, 1) == ls.LS_ERR_ARG
+        assert L.ls_server_set_precision(h, ls.PRECISION_MIXED) == ls.LS_OK
+        su_m = ctypes.c_int64()
+        assert L.ls_server_footprint(h, 1000, 10, 200, ctypes.byref(res_b), ctypes.byref(su_m)) == ls.LS_OK
+        assert su_m.value >= su_b.value + 4 * 200 * 11 + 8 * 200
+        assert sub() == ls.LS_ERR_DEVICE
+        assert L.ls_server_set_precision(h, ls.PRECISION_FP64) == ls.LS_OK
+        assert L.ls_server_footprint(h, 1000, 10, 200, ctypes.byref(res_b), ctypes.byref(su_m)) == ls.LS_OK
+        assert su_m.value == su_b.value
+        used = ctypes.c_int32()
+        assert L.ls_server_request_precision(h, 12345, ctypes.byref(used)) == ls.LS_ERR_ARG
+        assert L.ls_server_request_precision(h, 12345, None) == ls.LS_ERR_ARG
     finally:
         L.ls_server_destroy(h)

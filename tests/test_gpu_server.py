@@ -72,6 +72,91 @@ def test_served_equals_ls_solve_bitwise(ctx, probs, q):
         srv.close()
 
 
+@pytest.fixture(scope="module")
+def mixed_cases(probs):
+    """The problems above (kappa 1e2 to 1e12: the FP32 factor is taken, or refused by condest) and
+    one with d = n, where the iteration diverges although the FP32 factor is well conditioned (the
+    growth monitor fires)."""
+    spec = ProblemSpec(m=2000, n=20, kappa=1e3, beta=1e-3, d=20, seed=0)
+    p = make_problem_cpu(spec)
+    return [(sp, A, b) for sp, A, b, _ in probs] + [(spec, dev(p.A)[:, :20], dev(p.b))]
+
+
+def mixed_alone(ctx, cases, q):
+    """ls_solve with LS_OPT_PRECISION = 1 on each problem alone: (x, precision used)."""
+    out = []
+    ctx.set_option(ls.OPT_PRECISION, 1)
+    try:
+        for spec, A, b in cases:
+            ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+            x = ctx.solve(A, b, spec.d, q).clone()
+            out.append((x, ctx.solve_info()[4]))
+    finally:
+        ctx.set_option(ls.OPT_PRECISION, 0)
+    return out
+
+
+@pytest.mark.parametrize("q", [0, 7, 40])
+def test_served_mixed_equals_ls_solve_bitwise(ctx, mixed_cases, q):
+    ref = mixed_alone(ctx, mixed_cases, q)
+    srv = ls.Server(0, budget_bytes=64 << 30, max_active=64)
+    try:
+        srv.set_precision(ls.PRECISION_MIXED)
+        tk = [srv.submit(A, b, spec.d, q, spec.sketch_seed) for spec, A, b in mixed_cases]
+        for (t, x), (xr, used) in zip(tk, ref):
+            assert srv.wait(t, 120.0) == ls.LS_OK
+            assert srv.precision(t) == used
+            assert torch.equal(x, xr)
+        if q == 40:                               # every outcome occurs
+            assert {srv.precision(t) for t, _ in tk} == {
+                ls.PRECISION_MIXED, ls.PRECISION_FELL_BACK_COND, ls.PRECISION_FELL_BACK_GROWTH}
+        st = srv.stats()
+        assert st["finished"] == len(mixed_cases) and st["admitted"] == 0
+        assert st["footprint"] == st["setup_workspace"] > 0
+    finally:
+        srv.close()
+
+
+def test_served_mixed_and_fp64_together(ctx, probs, mixed_cases):
+    q = 12
+    ref64 = alone_results(ctx, probs, q)
+    refm = mixed_alone(ctx, mixed_cases[:len(probs)], q)
+    srv = ls.Server(0)
+    try:
+        tk = []
+        for k, (spec, A, b, _) in enumerate(probs):
+            srv.set_precision(ls.PRECISION_MIXED if k % 2 else ls.PRECISION_FP64)
+            tk.append(srv.submit(A, b, spec.d, q, spec.sketch_seed))
+        for k, ((t, x), r64, (rm, used)) in enumerate(zip(tk, ref64, refm)):
+            assert srv.wait(t, 120.0) == ls.LS_OK
+            if k % 2:
+                assert srv.precision(t) == used and torch.equal(x, rm)
+            else:
+                assert srv.precision(t) == ls.PRECISION_FP64 and torch.equal(x, r64)
+    finally:
+        srv.close()
+
+
+def test_served_mixed_growth_requeue_one_slot(ctx, mixed_cases):
+    """A request whose growth monitor fires is queued again, first, as an FP64 request: with one
+    slot the next request is admitted only after it has finished in FP64."""
+    cases = [mixed_cases[-1], mixed_cases[0], mixed_cases[-1]]
+    ref = mixed_alone(ctx, cases, 30)
+    assert [u for _, u in ref] == [ls.PRECISION_FELL_BACK_GROWTH, ls.PRECISION_MIXED, ls.PRECISION_FELL_BACK_GROWTH]
+    srv = ls.Server(0, max_active=1)
+    try:
+        srv.set_precision(ls.PRECISION_MIXED)
+        tk = [srv.submit(A, b, spec.d, 30, spec.sketch_seed) for spec, A, b in cases]
+        for (t, x), (xr, used) in zip(tk, ref):
+            assert srv.wait(t, 120.0) == ls.LS_OK
+            assert srv.precision(t) == used and torch.equal(x, xr)
+        times = [srv.times(t) for t, _ in tk]
+        assert times[1][1] >= times[0][3] and times[2][1] >= times[1][3]
+        assert srv.stats()["admitted"] == 0
+    finally:
+        srv.close()
+
+
 def test_served_alone_vs_mixed_bitwise(probs):
     spec, A, b, _ = probs[3]
     srv = ls.Server(0)
