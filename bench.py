@@ -447,51 +447,59 @@ def bench_served(args, w):
             out["per_request"] = [{"n": r["n"], "kappa": r["kappa"], "used": names[u]} for r, u in zip(reqs, used)]
         return out, xs
 
-    out = {}
-    out["served_saturation"], xs_sat = served(False)
-    print(f"[bench] served saturation: {out['served_saturation']}", file=sys.stderr, flush=True)
-    out["served_poisson"], _ = served(True)
-    print(f"[bench] served poisson: {out['served_poisson']}", file=sys.stderr, flush=True)
-    out["ls_solve_saturation"], xs_base = baseline(False)
-    print(f"[bench] ls_solve saturation: {out['ls_solve_saturation']}", file=sys.stderr, flush=True)
-    out["ls_solve_poisson"], _ = baseline(True)
-    print(f"[bench] ls_solve poisson: {out['ls_solve_poisson']}", file=sys.stderr, flush=True)
-    # The mixed-precision arm: the served stream with mixed precision (saturation and Poisson), and
-    # ls_solve with LS_OPT_PRECISION = 1 one request at a time (whose bits it must return).
-    out["served_mixed_saturation"], xs_smixed = served(False, precision=1)
-    print(f"[bench] served mixed saturation: {out['served_mixed_saturation']}", file=sys.stderr, flush=True)
-    out["served_mixed_poisson"], _ = served(True, precision=1)
-    print(f"[bench] served mixed poisson: {out['served_mixed_poisson']}", file=sys.stderr, flush=True)
-    out["ls_solve_mixed_saturation"], xs_mixed = baseline(False, precision=1)
-    print(f"[bench] ls_solve mixed saturation: "
-          f"{ {k: v for k, v in out['ls_solve_mixed_saturation'].items() if k != 'per_request'} }",
-          file=sys.stderr, flush=True)
-    fe_mixed = [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs_mixed, probs)]
-    same = all(torch.equal(a, b_) for a, b_ in zip(xs_sat, xs_base))
-    fe = [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs_sat, probs)]
+    # Arms (--served-arms picks some, e.g. one per profiled run): the served stream and ls_solve one
+    # request at a time, FP64, then with mixed precision (ls_solve mixed gives the bits the served
+    # mixed arm must return).
+    arms = {
+        "served_saturation": lambda: served(False),
+        "served_poisson": lambda: served(True),
+        "ls_solve_saturation": lambda: baseline(False),
+        "ls_solve_poisson": lambda: baseline(True),
+        "served_mixed_saturation": lambda: served(False, precision=1),
+        "served_mixed_poisson": lambda: served(True, precision=1),
+        "ls_solve_mixed_saturation": lambda: baseline(False, precision=1),
+    }
+    pick = set(args.served_arms.split(","))
+    out, xs = {}, {}
+    for name, run in arms.items():
+        if "all" in pick or name in pick:
+            out[name], xs[name] = run()
+            shown = {k: v for k, v in out[name].items() if k != "per_request"}
+            print(f"[bench] {name}: {shown}", file=sys.stderr, flush=True)
+
+    def rate(a, b_):
+        return out[a]["solves_per_s"] / out[b_]["solves_per_s"] if a in out and b_ in out else None
+
+    def same(a, b_):
+        return all(torch.equal(u, v) for u, v in zip(xs[a], xs[b_])) if a in xs and b_ in xs else None
+
+    def fes(a):
+        return [float(torch.linalg.norm(x - p[3]).item()) for x, p in zip(xs[a], probs)] if a in xs else None
+
+    fe, fe_mixed = fes("served_saturation"), fes("ls_solve_mixed_saturation")
+    sat = out.get("served_saturation")
     rec = {
         "metric": "served solves/s (saturation) with p50/p99 latency under Poisson arrivals",
-        "value": out["served_saturation"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": 1e3 * out["served_saturation"]["seconds"],
+        "value": sat["solves_per_s"] if sat else None, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": 1e3 * sat["seconds"] if sat else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "requests": len(reqs), "rate_per_s": w["rate"],
                    "m": [w["m_lo"], w["m_hi"]], "n": list(w["ns"]), "kappa": [w["kappa_lo"], w["kappa_hi"]],
                    "residual_norm": w["beta"], "d": "20n", "q": q, "zeta": w["zeta"],
-                   "resident_GB": resident / 1e9},
-        "speedup_saturation_vs_ls_solve": out["served_saturation"]["solves_per_s"] / out["ls_solve_saturation"]["solves_per_s"],
-        "bitwise_equal_to_ls_solve": same,
-        "forward_error_max": max(fe),
-        "mixed_vs_fp64_served_speedup": (out["served_mixed_saturation"]["solves_per_s"]
-                                         / out["served_saturation"]["solves_per_s"]),
-        "served_mixed_bitwise_equal_to_ls_solve_mixed": all(torch.equal(a, b_) for a, b_ in zip(xs_smixed, xs_mixed)),
-        "mixed_vs_fp64_ls_solve_speedup": (out["ls_solve_mixed_saturation"]["solves_per_s"]
-                                           / out["ls_solve_saturation"]["solves_per_s"]),
-        "forward_error_max_mixed": max(fe_mixed),
-        "forward_error_mixed_over_fp64_max": max(a / max(b_, 1e-300) for a, b_ in zip(fe_mixed, fe)),
+                   "resident_GB": resident / 1e9, "arms": sorted(out)},
+        "speedup_saturation_vs_ls_solve": rate("served_saturation", "ls_solve_saturation"),
+        "bitwise_equal_to_ls_solve": same("served_saturation", "ls_solve_saturation"),
+        "forward_error_max": max(fe) if fe else None,
+        "mixed_vs_fp64_served_speedup": rate("served_mixed_saturation", "served_saturation"),
+        "served_mixed_bitwise_equal_to_ls_solve_mixed": same("served_mixed_saturation", "ls_solve_mixed_saturation"),
+        "mixed_vs_fp64_ls_solve_speedup": rate("ls_solve_mixed_saturation", "ls_solve_saturation"),
+        "forward_error_max_mixed": max(fe_mixed) if fe_mixed else None,
+        "forward_error_mixed_over_fp64_max": (max(a / max(b_, 1e-300) for a, b_ in zip(fe_mixed, fe))
+                                              if fe and fe_mixed else None),
         **out,
     }
-    del probs, xs_sat, xs_base, xs_mixed, xs_smixed
+    del probs, xs
     release_device()
     print(json.dumps(rec), flush=True)
 
@@ -515,6 +523,10 @@ def main():
                     help="mixed workload: stop (Section 3.3 rule, q <= 200) and/or q40 (fixed q)")
     ap.add_argument("--qr-panel", type=int, default=0, choices=(0, 1),
                     help="LS_OPT_QR_PANEL: 0 cooperative panels, 1 one launch per column (same bits)")
+    ap.add_argument("--served-arms", default="all",
+                    help="served workload: comma list of arms to run (served_saturation, served_poisson, "
+                         "ls_solve_saturation, ls_solve_poisson, served_mixed_saturation, "
+                         "served_mixed_poisson, ls_solve_mixed_saturation), or all")
     ap.add_argument("--verbose", action="store_true", help="a progress line on stderr after every solve")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
