@@ -698,6 +698,70 @@ k_solve_served(const ServeSlot *__restrict__ slots)
         served_step<double, kSB>(sl, reinterpret_cast<double *>(smem), *reinterpret_cast<SubstLds<double, kSB> *>(lds), red);
 }
 
+// w = R v for upper triangular R, read through RT = R^T (ld n, zero above its diagonal): w_i is the
+// sum over j >= i of R[i][j] v_j, added in ascending j into one accumulator.  The lanes of a wave
+// own 64 consecutive outputs and walk the rows of RT together, so every load instruction reads 64
+// consecutive entries (a walk down R's rows or RT's columns would give each lane its own cache
+// line).  A wave starts at the row its lowest output needs; for a lane whose diagonal comes later,
+// the zero entries before it add +0 * v_j and leave its accumulator +0, so every sum is the one a
+// walk from j = i gives.  Blocks of 64 outputs are dealt to the waves in a zigzag (block w, then
+// the block mirrored from the end), which evens out the rows each wave walks.  v is in LDS.
+template <typename T, int U>
+__device__ __forceinline__ void upper_matvec(int64_t n, const T *__restrict__ RT, const T *v, T *__restrict__ w)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t nblk = (n + 63) / 64;
+    for (int64_t r = 0;; ++r) {
+        const int64_t blk = (r & 1) ? (r + 1) * nw - 1 - wave : r * nw + wave;
+        if (r * nw >= nblk) break;
+        if (blk >= nblk) continue;
+        const int64_t i0 = blk * 64, i = i0 + lane;
+        const T *col = RT + (i < n ? i : i0);       // the lane's column of RT (kept in the matrix)
+        T acc = T(0);
+        int64_t j = i0;
+        for (; j + U <= n; j += U) {
+            T a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = col[(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += a[u] * v[j + u];
+        }
+        for (; j < n; ++j) acc += col[j * n] * v[j];
+        if (i < n) w[i] = acc;
+    }
+}
+
+// v = R^T w for upper triangular R (ld ldr, zero below its diagonal): v_k is the sum over i <= k of
+// R[i][k] w_i, added in ascending i into one accumulator.  As in upper_matvec the lanes own 64
+// consecutive outputs and walk R's rows together, here up to the last row the block's highest
+// output needs; the zero entries after a lane's diagonal add +-0 and leave its sum unchanged (but
+// for the sign of an exactly zero sum).  w is in LDS.
+template <typename T, int U>
+__device__ __forceinline__ void lower_matvec(int64_t n, const T *__restrict__ R, int64_t ldr, const T *w, T *__restrict__ v)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t nblk = (n + 63) / 64;
+    for (int64_t r = 0;; ++r) {
+        const int64_t blk = (r & 1) ? (r + 1) * nw - 1 - wave : r * nw + wave;
+        if (r * nw >= nblk) break;
+        if (blk >= nblk) continue;
+        const int64_t k0 = blk * 64, k = k0 + lane;
+        const int64_t iend = (k0 + 64 < n) ? k0 + 64 : n;   // rows 0 .. iend - 1
+        const T *col = R + (k < n ? k : k0);
+        T acc = T(0);
+        int64_t i = 0;
+        for (; i + U <= iend; i += U) {
+            T a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = col[(i + u) * ldr];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += a[u] * w[i + u];
+        }
+        for (; i < iend; ++i) acc += col[i * ldr] * w[i];
+        if (k < n) v[k] = acc;
+    }
+}
+
 // Section 3.3 estimators, one work-group, in the arithmetic of the factor (T).
 //   normest: v = g/||g|| with g_i uniform on [-1, 1) (53 high bits of SplitMix64 output i of the
 //            stream `seed`); ceil(ln n) times: w = R v, est = ||w||, v = R^T w / ||R^T w||.
@@ -736,19 +800,19 @@ k_estimators(int64_t n, const T *__restrict__ R, int64_t ldr, const T *__restric
     if (steps < 1) steps = 1;
     T est = T(0);
     for (int it = 0; it < steps; ++it) {
-        for (int64_t i = tid; i < n; i += blockDim.x)       // w = R v, one row per thread, read as
-            w[i] = strided_dot<8>(RT + i * n + i, n, v + i, (int)(n - i));   // a column of R^T
-
+        for (int64_t i = tid; i < n; i += blockDim.x) s[i] = v[i];
+        __syncthreads();
+        upper_matvec<T, 16>(n, RT, s, w);                   // w = R v
         __syncthreads();
         T ww = T(0);
         for (int64_t i = tid; i < n; i += blockDim.x) ww += w[i] * w[i];
         est = sqrt(block_sum(ww, red));
+        for (int64_t i = tid; i < n; i += blockDim.x) s[i] = w[i];
+        __syncthreads();
+        lower_matvec<T, 16>(n, R, ldr, s, v);               // v = R^T w
+        __syncthreads();
         T vv = T(0);
-        for (int64_t k = tid; k < n; k += blockDim.x) {      // v = R^T w, one column per thread
-            const T a = strided_dot<8>(R + k, ldr, (const T *)w, (int)(k + 1));
-            v[k] = a;
-            vv += a * a;
-        }
+        for (int64_t k = tid; k < n; k += blockDim.x) vv += v[k] * v[k];
         vv = sqrt(block_sum(vv, red));
         if (vv == T(0)) break;
         for (int64_t k = tid; k < n; k += blockDim.x) v[k] /= vv;
