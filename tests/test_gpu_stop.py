@@ -54,6 +54,26 @@ def test_stopping_rule_matches_oracle(ctx, kappa, beta):
     assert np.linalg.norm(x - p.x_true) <= 10 * max(fe_h, 1e-15) + 1e-15
 
 
+@pytest.mark.parametrize("n", [1, 7, 63, 64, 65, 130, 333])
+def test_estimators_match_oracle_across_sizes(ctx, n):
+    """normest and condest at widths below one wave, at one and just past one block of 64 outputs,
+    and with a ragged last block (the power-method products deal 64-output blocks to the waves)."""
+    spec = ProblemSpec(m=4000, n=n, kappa=1e3, beta=1e-6, d=max(1000, 4 * n), seed=11)
+    p = make_problem_cpu(spec)
+    seed = spec.sketch_seed
+    g = oracle.normest_start(n, (seed + ls.NORMEST_SEED_OFFSET) % (1 << 64))
+    _, _, ne_o, ce_o = oracle.iterative_sketching_stop(p.A, p.b, n, spec.d, 2, g, seed=seed)
+    ctx.set_option(ls.OPT_SEED, seed)
+    ctx.set_option(ls.OPT_STOP, 1)
+    try:
+        ctx.solve(dev(p.A)[:, :n], dev(p.b), spec.d, 2)
+        _, _, ne, ce, _ = ctx.solve_info()
+    finally:
+        ctx.set_option(ls.OPT_STOP, 0)
+    assert abs(ne - ne_o) <= 1e-8 * ne_o
+    assert ce_o / 3 <= ce <= 3 * ce_o
+
+
 def test_stopping_rule_fewer_steps_and_q_cap(ctx):
     spec = ProblemSpec(m=4000, n=50, kappa=1e10, beta=1e-6, d=1000, seed=9)
     p = make_problem_cpu(spec)
