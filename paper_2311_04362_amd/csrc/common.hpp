@@ -154,7 +154,8 @@ struct SketchBufs {
     int32_t *rowptr = nullptr;     // d+1
     int32_t *fill = nullptr;       // d
     uint32_t *cols = nullptr;      // m*zeta packed (j | sign<<31), by sketch row, ascending j (null when win.direct)
-    int32_t *chunk_cnt = nullptr;  // ceil(m / 8192) x d per-chunk row counts (8192 zeta / 8 <= d <= 40960), else null
+    int32_t *chunk_cnt = nullptr;  // ceil(m / chunk_cols) x d per-chunk row counts (chunk path), else null
+    int32_t chunk_cols = 0;        // columns of S per chunk: 8192, halved while chunk_cols zeta > 8 d (>= 256)
     WinLists win;        // built by launch_csr when active (without the CSR when win.direct)
 };
 // n > 0 and win_mode == 0: also carve the lists of the column-sliced gather when the shape suits it.

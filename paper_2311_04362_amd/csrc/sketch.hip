@@ -193,24 +193,27 @@ k_csr_sort(int64_t d, const int32_t *__restrict__ rowptr, uint32_t *__restrict__
 }
 
 // ---- CSR by chunk histograms (d <= kLdsRows) -------------------------------------------------------
-// The columns of S are cut into chunks of kChunkCols.  A work-group counts its chunk's nonzeros per
+// The columns of S are cut into chunks of cc columns (cc = kChunkCols, halved while a (chunk, row)
+// segment would hold more than 8 entries on average, down to kMinChunkCols, so that small d keep
+// short segments too).  A work-group counts its chunk's nonzeros per
 // sketch row in LDS; the counts are summed over chunks (row lengths, then rowptr by k_scan_rows) and
 // turned in place into each (chunk, row) segment's start; a work-group then places its chunk's
 // nonzeros in their segments (LDS counters) and sorts each segment, a handful of entries, by j.
 // Segments of one row follow chunk order, so every row ends in ascending j: the CSR of k_csr_sort.
 constexpr int kChunkCols = 8192;
+constexpr int kMinChunkCols = 256;
 constexpr int64_t kLdsRows = 40960;      // 160 KiB of int32 counters
 
 __global__ void __launch_bounds__(1024)
-k_chunk_hist(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ ent,
+k_chunk_hist(int64_t m, int64_t d, int32_t zeta, int64_t cc, const uint32_t *__restrict__ ent,
              int32_t *__restrict__ cnt)
 {
     __shared__ int32_t h[kLdsRows];
     const int64_t c = blockIdx.x;
     for (int64_t k = threadIdx.x; k < d; k += blockDim.x) h[k] = 0;
     __syncthreads();
-    const int64_t j1 = ((c + 1) * kChunkCols < m) ? (c + 1) * kChunkCols : m;
-    for (int64_t i = c * kChunkCols * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x)
+    const int64_t j1 = ((c + 1) * cc < m) ? (c + 1) * cc : m;
+    for (int64_t i = c * cc * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x)
         atomicAdd(&h[ent[i] & 0x7FFFFFFFu], 1);
     __syncthreads();
     for (int64_t k = threadIdx.x; k < d; k += blockDim.x) cnt[c * d + k] = h[k];
@@ -251,7 +254,7 @@ k_chunk_base(int64_t d, int32_t nchunk, const int32_t *__restrict__ rowptr, int3
 }
 
 __global__ void __launch_bounds__(1024)
-k_chunk_place(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ ent,
+k_chunk_place(int64_t m, int64_t d, int32_t zeta, int64_t cc, const uint32_t *__restrict__ ent,
               const int32_t *__restrict__ base, uint32_t *__restrict__ cols)
 {
     __shared__ int32_t pos[kLdsRows];
@@ -259,8 +262,8 @@ k_chunk_place(int64_t m, int64_t d, int32_t zeta, const uint32_t *__restrict__ e
     const int32_t *b = base + c * d;
     for (int64_t k = threadIdx.x; k < d; k += blockDim.x) pos[k] = b[k];
     __syncthreads();
-    const int64_t j1 = ((c + 1) * kChunkCols < m) ? (c + 1) * kChunkCols : m;
-    for (int64_t i = c * kChunkCols * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x) {
+    const int64_t j1 = ((c + 1) * cc < m) ? (c + 1) * cc : m;
+    for (int64_t i = c * cc * zeta + threadIdx.x; i < j1 * zeta; i += blockDim.x) {
         const uint32_t v = ent[i];
         const int32_t p = atomicAdd(&pos[v & 0x7FFFFFFFu], 1);
         cols[p] = (uint32_t)(i / zeta) | (v & 0x80000000u);
@@ -862,11 +865,14 @@ void sketch_bufs(Arena &ar, int64_t m, int64_t d, int32_t zeta, SketchBufs &sb, 
     }
     sb.cols = ar.take<uint32_t>(nnz);
     // The chunk path needs the counters in LDS (d <= kLdsRows), short segments (a (chunk, row)
-    // segment holds kChunkCols zeta / d entries on average: at most 8, so the register sort takes
-    // nearly all of them) and a bounded count matrix.
-    const size_t chunk_cells = (size_t)((m + kChunkCols - 1) / kChunkCols) * (size_t)d;
-    const bool chunk_path = d <= kLdsRows && 8 * d >= (int64_t)kChunkCols * zeta && chunk_cells <= ((size_t)1 << 26);
+    // segment holds cc zeta / d entries on average: at most 8, so the register sort takes nearly
+    // all of them) and a bounded count matrix.
+    int64_t cc = kChunkCols;
+    while (cc > kMinChunkCols && cc * zeta > 8 * d) cc >>= 1;
+    const size_t chunk_cells = (size_t)((m + cc - 1) / cc) * (size_t)d;
+    const bool chunk_path = d <= kLdsRows && 8 * d >= cc * zeta && chunk_cells <= ((size_t)1 << 26);
     sb.chunk_cnt = chunk_path ? ar.take<int32_t>(chunk_cells) : nullptr;
+    sb.chunk_cols = chunk_path ? (int32_t)cc : 0;
 }
 
 hipError_t launch_sparse_sign(hipStream_t s, int64_t m, int64_t d, int32_t zeta, uint64_t seed,
@@ -919,12 +925,13 @@ hipError_t launch_csr(hipStream_t s, int64_t m, int64_t d, int32_t zeta, const S
         return hipGetLastError();
     }
     if (sb.chunk_cnt) {
-        const int32_t nchunk = (int32_t)((m + kChunkCols - 1) / kChunkCols);
-        hipLaunchKernelGGL(k_chunk_hist, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, sb.ent, sb.chunk_cnt);
+        const int64_t cc = sb.chunk_cols;
+        const int32_t nchunk = (int32_t)((m + cc - 1) / cc);
+        hipLaunchKernelGGL(k_chunk_hist, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, cc, sb.ent, sb.chunk_cnt);
         hipLaunchKernelGGL(k_chunk_total, dim3(blocks_for(d, 256)), dim3(256), 0, s, d, nchunk, sb.chunk_cnt, sb.rowcount);
         hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, d, sb.rowcount, sb.rowptr, sb.fill);
         hipLaunchKernelGGL(k_chunk_base, dim3(blocks_for(d, 256)), dim3(256), 0, s, d, nchunk, sb.rowptr, sb.chunk_cnt);
-        hipLaunchKernelGGL(k_chunk_place, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, sb.ent, sb.chunk_cnt, sb.cols);
+        hipLaunchKernelGGL(k_chunk_place, dim3((unsigned)nchunk), dim3(1024), 0, s, m, d, zeta, cc, sb.ent, sb.chunk_cnt, sb.cols);
     } else {
         hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, s, d, sb.rowcount, sb.rowptr, sb.fill);
         hipLaunchKernelGGL(k_csr_scatter, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, zeta, sb.ent,

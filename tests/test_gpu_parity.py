@@ -65,8 +65,12 @@ def test_embedding_bit_exact(ctx, m, d, zeta, seed):
                                            (200000, 10000, 8, 11),
                                            (100000, 40960, 8, 6),  # largest d of the chunked CSR
                                            (100000, 40961, 8, 6),  # past it: atomic CSR
-                                           (20000, 8192, 8, 7),    # smallest d of the chunked CSR
-                                           (20000, 8191, 8, 7)])   # below it: atomic CSR
+                                           (20000, 8192, 8, 7),    # 8192-column chunks
+                                           (20000, 8191, 8, 7),    # 4096-column chunks
+                                           (78173, 640, 8, 3),     # 512-column chunks, ragged last
+                                           (200003, 5120, 8, 9),   # 4096-column chunks, ragged last
+                                           (20000, 256, 8, 7),     # smallest d of the chunked CSR
+                                           (20000, 255, 8, 7)])    # below it: atomic CSR
 def test_csr_bit_exact(ctx, m, d, zeta, seed):
     rowptr, cols = ctx.sketch_csr(m, d, zeta, seed)
     erp, ec = expected_csr(m, d, zeta, seed)
