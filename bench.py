@@ -403,17 +403,23 @@ def bench_served(args, w):
         th.join()
         status = [srv.wait(t) for t in tickets]
         t_end = time.perf_counter()
-        lat = []
+        lat, wait, setup, rounds = [], [], [], []
         for t in tickets:
-            t0, _, _, t3 = srv.times(t)
+            t0, t1, t2, t3 = srv.times(t)
             lat.append(t3 - t0)
+            wait.append(t1 - t0)
+            setup.append(t2 - t1)
+            rounds.append(t3 - t2)
         used = [srv.precision(t) for t in tickets]
         stats = srv.stats()
         srv.close()
         out = {"seconds": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
                "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
                "rounds": stats["rounds"], "failed": sum(1 for s_ in status if s_ != ls.LS_OK),
-               "footprint_peak_GB": stats["footprint_peak"] / 1e9}
+               "footprint_peak_GB": stats["footprint_peak"] / 1e9,
+               # medians of the phases of a request: queued until admitted, set up, iterated
+               "p50_phase_ms": {"queued": 1e3 * pct(wait, 50), "setup": 1e3 * pct(setup, 50),
+                                "rounds": 1e3 * pct(rounds, 50)}}
         if precision:
             out["precision_used"] = {nm: sum(1 for u in used if u == k) for k, nm in enumerate(names)}
         return out, xs
