@@ -223,11 +223,11 @@ ls_status ls_precond_solve_f32(ls_ctx *ctx, void *stream, int64_t n, const float
  * returns for it alone with the same precision option.  Problems are admitted first
  * in, first out while the footprint stays within `budget_bytes` and at most `max_active` are
  * admitted.  The footprint counts, for every admitted problem, its resident bytes (A and b, 8mn + 8m,
- * plus its device block: R, R^T, pass partials, c) and the workspaces the four setup lanes hold
+ * plus its device block: R, R^T, pass partials, c) and the workspaces the eight setup lanes hold
  * (embedding, lists, sketch and QR work matrix of the largest problem each set up; an idle lane
  * gives its workspace back when the next problem would not fit otherwise); ls_server_footprint
  * reports both figures for a shape.  The sketch, QR and
- * start of each are computed on one of four setup streams (four problems at a time), then every
+ * start of each are computed on one of eight setup streams (eight problems at a time), then every
  * admitted problem takes one refinement step per round on a serve stream (one batched launch per
  * kernel for all of them: continuous batching -- problems join and leave between rounds).  A
  * scheduler thread owned by the server does all device work.  A, b and x are device pointers owned
