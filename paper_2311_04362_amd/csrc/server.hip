@@ -37,7 +37,8 @@ using Clock = std::chrono::steady_clock;
 constexpr int kRoundsInFlight = 3;     // rounds enqueued ahead of the host
 // Setups in flight at once, each on its own stream.  Setups are chains of small latency-bound
 // launches, so more of them overlap better: 8 lanes measured 925-947 solves/s at saturation against
-// 886-899 for 4 under HIP's default four hardware queues (839 with eight queues).
+// 886-899 for 4 under HIP's default four hardware queues (839 with eight queues; 12 lanes 890-918,
+// 16 lanes 860-873).
 constexpr int kSetupLanes = 8;
 constexpr int kClasses = 9;            // pass classes (pass_class)
 
