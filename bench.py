@@ -538,7 +538,7 @@ def main():
                     help="also time a plain elementwise copy kernel of 2 GiB (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build",
+        print("bench.py: the solver runs on one GPU; --gpus above 1 (or WORLD_SIZE > 1) is not supported",
               file=sys.stderr)
         sys.exit(2)
 

@@ -41,13 +41,13 @@ typedef enum {
     LS_ERR_RANK = 4,         /* deferred: |R_kk| <= n u max_j |R_jj| (A taken as rank deficient) */
     LS_ERR_NONFINITE = 5,    /* deferred: NaN or Inf met in B, R or x                            */
     LS_ERR_DIVERGED = 6,     /* deferred: the stopping rule saw the residual grow without bound  */
-    LS_ERR_UNSUPPORTED = 7,  /* a size outside what this build handles (see ls_limits)           */
+    LS_ERR_UNSUPPORTED = 7,  /* a size beyond the library's compiled limits (see ls_limits)      */
     LS_ERR_TIMEOUT = 8       /* ls_server_wait: the request did not finish within the timeout    */
 } ls_status;
 
 typedef struct ls_ctx ls_ctx;
 
-/* Limits of this build (returned by ls_limits). */
+/* Compiled limits of the library (returned by ls_limits). */
 #define LS_MAX_ZETA 32       /* nonzeros per column of S                                         */
 #define LS_MAX_N 2048        /* columns of A                                                     */
 
