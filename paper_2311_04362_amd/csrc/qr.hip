@@ -678,7 +678,12 @@ k_tz(int nch, int64_t ldo, const E *__restrict__ P, const E *__restrict__ tau, i
 }
 
 // C[r][c] -= sum_a V[r][a] Z[a][c] over rows r < rows, columns c < nc.
-// Work-group tile 64 x 64: wave w owns rows 16w..16w+15 and four 16-column MFMA blocks.
+// Work-group tile 256 x 64: wave w owns rows 64w..64w+63 in four 16-row blocks and four 16-column
+// MFMA blocks.  The wave loads its 32 x 64 slice of Z once and keeps it in registers for its four
+// row blocks (Z was reloaded for every 16 rows before: more load instructions than C itself).  Each
+// entry's products are accumulated over a in the same order as before, so the bits are the same.
+constexpr int kUpdRows = 256;
+
 template <typename E>
 __global__ void __launch_bounds__(256)
 k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restrict__ Z,
@@ -686,44 +691,52 @@ k_update_c(int64_t rows, int64_t nc, const E *__restrict__ V, const E *__restric
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t rblk, cblk;
-    if (!xcd_tile(blockIdx.x, (rows + 63) / 64, (nc + 63) / 64, rblk, cblk)) return;
-    const int64_t r0 = rblk * 64 + 16 * wave;
+    if (!xcd_tile(blockIdx.x, (rows + kUpdRows - 1) / kUpdRows, (nc + 63) / 64, rblk, cblk)) return;
     const int64_t c0 = cblk * 64;
     const int kk = lane >> 4, ii = lane & 15;
-    const int64_t ra = r0 + ii;
-    const bool ra_ok = ra < rows;
-    // this lane's 16 entries of C, loaded first so that their latency overlaps the products
-    E cv[4][4];
+    // this lane's operands of Z: row a + kk, column c0 + 16 cb + ii, for a = 0, 4, ..., kNB - 4
+    E zv[kNB / 4][4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         const int64_t cc = c0 + 16 * cb + ii;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t r = r0 + Mfma<E>::row(q, lane);
-            cv[cb][q] = (cc < nc && r < rows) ? C[r * ldc + cc] : E(0);
-        }
+        for (int a4 = 0; a4 < kNB / 4; ++a4)
+            zv[a4][cb] = (cc < nc) ? Z[(int64_t)(4 * a4 + kk) * ldz + cc] : E(0);
     }
-    typename Mfma<E>::v4 acc[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
-#pragma unroll
-    for (int a = 0; a < kNB; a += 4) {
-        const E av = ra_ok ? V[ra * kNB + a + kk] : E(0);
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t r0 = rblk * kUpdRows + 64 * wave + 16 * rb;
+        if (r0 >= rows) break;
+        const int64_t ra = r0 + ii;
+        const bool ra_ok = ra < rows;
+        // this lane's 16 entries of C, loaded first so that their latency overlaps the products
+        E cv[4][4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int64_t cc = c0 + 16 * cb + ii;
-            const E bv = (cc < nc) ? Z[(int64_t)(a + kk) * ldz + cc] : E(0);
-            acc[cb] = Mfma<E>::mma(av, bv, acc[cb]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + Mfma<E>::row(q, lane);
+                cv[cb][q] = (cc < nc && r < rows) ? C[r * ldc + cc] : E(0);
+            }
         }
-    }
+        typename Mfma<E>::v4 acc[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        const int64_t cc = c0 + 16 * cb + ii;
-        if (cc >= nc) continue;
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = (typename Mfma<E>::v4){E(0), E(0), E(0), E(0)};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t r = r0 + Mfma<E>::row(q, lane);
-            if (r < rows) C[r * ldc + cc] = cv[cb][q] - acc[cb][q];
+        for (int a4 = 0; a4 < kNB / 4; ++a4) {
+            const E av = ra_ok ? V[ra * kNB + 4 * a4 + kk] : E(0);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[cb] = Mfma<E>::mma(av, zv[a4][cb], acc[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int64_t cc = c0 + 16 * cb + ii;
+            if (cc >= nc) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + Mfma<E>::row(q, lane);
+                if (r < rows) C[r * ldc + cc] = cv[cb][q] - acc[cb][q];
+            }
         }
     }
 }
@@ -959,7 +972,7 @@ void trailing_update(hipStream_t s, int64_t d, int64_t n, const QrBufsT<E> &qb, 
                        nch, ldo, (int64_t)kNB + nc, Yp);
     hipLaunchKernelGGL(k_tz<E>, dim3((unsigned)ceil_div(nc, 64)), dim3(1024), 0, s, 1, ldo, Yp,
                        qb.tau, p0, nbp, nc, Z, ldw);
-    hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)(8 * ceil_div(ceil_div(rows, 64), 8) * ceil_div(nc, 64))),
+    hipLaunchKernelGGL(k_update_c<E>, dim3((unsigned)(8 * ceil_div(ceil_div(rows, kUpdRows), 8) * ceil_div(nc, 64))),
                        dim3(256), 0, s, rows, nc, V, Z, ldw, qb.W + p0 * ldw + c0, ldw);
 }
 
