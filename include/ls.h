@@ -55,7 +55,7 @@ typedef struct ls_ctx ls_ctx;
  * device >= 0 selects a GPU.  device = -1 creates a host-only context that validates arguments
  * and then returns LS_ERR_DEVICE from every compute call (for testing argument checks without a
  * GPU).  Returns LS_ERR_DEVICE if the GPU cannot be used.  The first QR of a large sketch
- * (d*n >= 6e7, cooperative panels) also creates one non-blocking side stream and two events in
+ * (d*n >= 3e7, cooperative panels) also creates one non-blocking side stream and two events in
  * the context; that QR's trailing updates run partly on it, joined back into the caller's stream
  * by events before the call's later work, so ordering on the caller's stream is unchanged. */
 ls_status ls_create(int device, ls_ctx **out);

@@ -201,9 +201,10 @@ struct QrBufsT {
 using QrBufs = QrBufsT<double>;
 using QrBufs32 = QrBufsT<float>;
 // The look-ahead pays when the trailing updates it overlaps with the panels are large: measured with
-// cooperative panels, 40.2 -> 35.4 ms at d = 4e4, n = 2000, but 4.20 -> 4.32 ms at d = 1e4, n = 500
-// and 10.80 -> 10.96 ms at d = 2e4, n = 1000 (stream and event costs per panel).
-inline bool qr_lookahead_pays(int64_t d, int64_t n) { return (double)d * (double)n >= 6e7; }
+// cooperative panels, 40.2 -> 35.4 ms at d = 4e4, n = 2000 and 19.7 -> 19.0 ms at d = 3e4, n = 1500,
+// but 4.20 -> 4.32 ms at d = 1e4, n = 500 and 9.77 -> 9.90 ms at d = 2e4, n = 1000 (stream and
+// event costs per panel).
+inline bool qr_lookahead_pays(int64_t d, int64_t n) { return (double)d * (double)n >= 3e7; }
 void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs &qb, bool lookahead = false);
 void qr_bufs(Arena &ar, int64_t d, int64_t n, QrBufs32 &qb, bool lookahead = false);
 hipError_t launch_copy_sketch(hipStream_t s, int64_t d, int64_t n, const double *B, int64_t ldb,

@@ -154,7 +154,8 @@ def test_qr_sketch_vs_oracle(ctx, d, n, kappa, panel):
 # per-column path on one stream.
 # d = 33000, n = 300: the first eight panels have 65 work-groups (step-flag barrier), the last two
 # 64 (arrival-counter barrier), in one factorization.
-@pytest.mark.parametrize("d,n", [(3000, 70), (8191, 70), (8192, 70), (12001, 70), (30000, 2010), (33000, 300)])
+@pytest.mark.parametrize("d,n", [(3000, 70), (8191, 70), (8192, 70), (12001, 70), (30000, 2010), (33000, 300),
+                                 (20003, 1500), (14999, 2000)])   # just above / below d n = 3e7
 def test_qr_panel_paths_agree_bitwise(ctx, d, n):
     """Both panel implementations, with or without the look-ahead, do the same arithmetic in the
     same order."""
