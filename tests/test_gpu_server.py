@@ -157,6 +157,30 @@ def test_served_mixed_growth_requeue_one_slot(ctx, mixed_cases):
         srv.close()
 
 
+def test_served_mixed_under_tight_budget(ctx, mixed_cases):
+    """Mixed requests, growth fallbacks among them, under a budget that admits only a few problems
+    at a time: every request still finishes with ls_solve's bits, and the footprint stays within
+    the budget (a re-queued request gives its block back before it is admitted again)."""
+    cases = [mixed_cases[-1], mixed_cases[0], mixed_cases[3], mixed_cases[-1], mixed_cases[5]]
+    ref = mixed_alone(ctx, cases, 12)
+    probe = ls.Server(0, budget_bytes=1 << 40, max_active=8)
+    probe.set_precision(ls.PRECISION_MIXED)
+    fps = [probe.footprint(spec.m, spec.n, spec.d) for spec, _, _ in cases]
+    probe.close()
+    budget = max(r + s_ for r, s_ in fps) + min(r for r, _ in fps)
+    srv = ls.Server(0, budget_bytes=budget, max_active=8)
+    try:
+        srv.set_precision(ls.PRECISION_MIXED)
+        tk = [srv.submit(A, b, spec.d, 12, spec.sketch_seed) for spec, A, b in cases]
+        for (t, x), (xr, used) in zip(tk, ref):
+            assert srv.wait(t, 120.0) == ls.LS_OK
+            assert srv.precision(t) == used and torch.equal(x, xr)
+        st = srv.stats()
+        assert st["footprint_peak"] <= budget and st["admitted"] == 0 and st["finished"] == len(cases)
+    finally:
+        srv.close()
+
+
 def test_served_alone_vs_mixed_bitwise(probs):
     spec, A, b, _ = probs[3]
     srv = ls.Server(0)
