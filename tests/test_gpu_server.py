@@ -157,6 +157,28 @@ def test_served_mixed_growth_requeue_one_slot(ctx, mixed_cases):
         srv.close()
 
 
+def test_served_mixed_wide_rows_bitwise(ctx):
+    """n = 600: ls_solve's FP32 solves read four floats per load above n = 512, the served solve
+    one; the sums, and so the bits, are the same (FP64 and mixed requests)."""
+    spec = ProblemSpec(m=30000, n=600, kappa=1e2, beta=1e-6, d=12000, seed=77)
+    p = make_problem_cpu(spec)
+    A, b = dev(p.A)[:, :600], dev(p.b)
+    (xm, used), = mixed_alone(ctx, [(spec, A, b)], 9)
+    assert used == ls.PRECISION_MIXED
+    ctx.set_option(ls.OPT_SEED, spec.sketch_seed)
+    x64 = ctx.solve(A, b, spec.d, 9).clone()
+    srv = ls.Server(0)
+    try:
+        t64, y64 = srv.submit(A, b, spec.d, 9, spec.sketch_seed)
+        srv.set_precision(ls.PRECISION_MIXED)
+        tm, ym = srv.submit(A, b, spec.d, 9, spec.sketch_seed)
+        assert srv.wait(t64, 120.0) == ls.LS_OK and srv.wait(tm, 120.0) == ls.LS_OK
+        assert srv.precision(tm) == ls.PRECISION_MIXED
+        assert torch.equal(y64, x64) and torch.equal(ym, xm)
+    finally:
+        srv.close()
+
+
 def test_served_mixed_under_tight_budget(ctx, mixed_cases):
     """Mixed requests, growth fallbacks among them, under a budget that admits only a few problems
     at a time: every request still finishes with ls_solve's bits, and the footprint stays within
